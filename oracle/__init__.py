@@ -1,0 +1,90 @@
+"""CPU oracle for the stencil sweeps -- TEST INFRASTRUCTURE ONLY.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package.  It wraps the plain C sweep in
+``oracle.c`` (naive (d+1)-loop sweep of Section 1 / Algorithm 1, Gauss-Seidel
+in place as in Section 3.4), which shares no code with the HIP library.
+
+Every function here is pinned by ``tests/test_oracle_pins.py`` against exact
+rational brute force, eigenmode closed forms and invariants.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Sequence
+
+import numpy as np
+
+STAR, BOX = 0, 1
+JACOBI, GAUSS_SEIDEL = 0, 1
+DIRICHLET, PERIODIC = 0, 1
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        from . import build as _build  # compile on first use (gcc only)
+        _build.build()
+    lib = ctypes.CDLL(_LIB_PATH)
+    i64p = ctypes.POINTER(ctypes.c_int64)
+    for name, real in (("oracle_sweep_f64", ctypes.c_double), ("oracle_sweep_f32", ctypes.c_float)):
+        fn = getattr(lib, name)
+        fn.argtypes = [ctypes.c_int, i64p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                       ctypes.POINTER(real), ctypes.c_int64, ctypes.POINTER(real)]
+        fn.restype = ctypes.c_int
+    lib.oracle_offsets.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                   ctypes.POINTER(ctypes.c_int)]
+    lib.oracle_offsets.restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+class OracleError(RuntimeError):
+    pass
+
+
+def offsets(ndim: int, shape: int, npoints: int) -> np.ndarray:
+    """Canonical offset list (lexicographic, axis 0 most significant)."""
+    lib = _load()
+    buf = (ctypes.c_int * (npoints * ndim))()
+    P = lib.oracle_offsets(ndim, shape, npoints, buf)
+    if P < 0:
+        raise OracleError(f"oracle_offsets failed ({P})")
+    return np.array(buf[:], dtype=np.int64).reshape(P, ndim)
+
+
+def sweep(u: np.ndarray, coeffs: Sequence[float], shape: int, dependence: int, boundary: int,
+          T: int, npoints: int | None = None, precision: str = "f64") -> np.ndarray:
+    """Return u after T steps of the naive sweep (the input is not modified).
+
+    ``precision="f64"`` (the reference) widens the input to float64 and uses
+    the coefficients as given.  ``precision="f32"`` repeats the identical
+    operation sequence in single precision with coefficients rounded to
+    float32 (round to nearest even).
+    """
+    lib = _load()
+    if npoints is None:
+        npoints = len(coeffs)
+    if len(coeffs) != npoints:
+        raise OracleError("coefficient count differs from the point count")
+    if precision == "f64":
+        real, fn, np_real = ctypes.c_double, lib.oracle_sweep_f64, np.float64
+    elif precision == "f32":
+        real, fn, np_real = ctypes.c_float, lib.oracle_sweep_f32, np.float32
+    else:
+        raise OracleError(f"unknown precision {precision!r}")
+    g = np.ascontiguousarray(u, dtype=np_real).copy()
+    c = np.ascontiguousarray(np.asarray(coeffs, dtype=np.float64).astype(np_real))
+    dims = (ctypes.c_int64 * g.ndim)(*g.shape)
+    rc = fn(g.ndim, dims, shape, npoints, dependence, boundary,
+            c.ctypes.data_as(ctypes.POINTER(real)), int(T), g.ctypes.data_as(ctypes.POINTER(real)))
+    if rc != 0:
+        raise OracleError(f"oracle sweep failed ({rc})")
+    return g

@@ -1,0 +1,203 @@
+/*
+ * Stencil oracle -- TEST INFRASTRUCTURE ONLY.
+ *
+ * A plain, single-threaded, deliberately slow CPU implementation of the
+ * time-iterated stencil sweep that the HIP library computes.  Only the test
+ * suite, the smoke check and the benchmark's CPU-baseline leg use it; the
+ * product path never calls, links or loads it.  It shares no code with the
+ * HIP library.
+ *
+ * What it computes (Section 1 of the paper, the problem statement, and the
+ * scalar 1D3P Jacobi code of Algorithm 1 in Section 2.1; Gauss-Seidel as
+ * described in Section 3.4 "Gauss-Seidel stencils"):
+ *
+ *   - a regular d-dimensional grid u (d = 1, 2, 3), C order (axis 0 slowest);
+ *   - a stencil of P points given by its shape (star or box) and radius r,
+ *     P = 2*d*r + 1 (star) or (2r+1)^d (box);
+ *   - the naive (d+1)-loop sweep: the outermost loop runs over time, the
+ *     inner loops over the grid points in lexicographic order;
+ *   - each point update is the weighted sum of its P neighbours,
+ *       acc = c[0]*v[0];  acc = acc + c[q]*v[q]  for q = 1 .. P-1,
+ *     with the offsets in canonical order: lexicographic over the offset
+ *     vector, axis 0 most significant.  Every product and every sum is a
+ *     separately rounded IEEE operation (this file must be compiled with
+ *     -ffp-contract=off and without fast-math);
+ *   - Jacobi: every update of step t+1 reads step-t values (a second buffer);
+ *   - Gauss-Seidel: a single array updated in place in lexicographic order,
+ *     so neighbours that come earlier in that order contribute their newest
+ *     (this step's) value and the centre and later neighbours their previous
+ *     one;
+ *   - constant (Dirichlet) boundary: the outer r layers of every axis are
+ *     part of the array, never written, and read as fixed values;
+ *     periodic boundary: every point is updated and neighbour indices wrap.
+ *
+ * The FP32 entry points repeat the same loops in single precision (storage,
+ * coefficients and arithmetic all float, same operation order).  They exist so
+ * that the single-precision GPU path, which follows the same operation order,
+ * can be checked bit for bit; the reference result for error statements is
+ * the FP64 sweep.
+ *
+ * Pinned by tests that do not use this file's arithmetic: exact rational
+ * brute force (Jacobi iteration matrix, Gauss-Seidel triangular solve),
+ * Fourier and sine eigenmodes, the binomial closed form of the 1D 3-point
+ * smoother, constant fields, fixed borders, translation invariance,
+ * composition, the maximum principle, and the Gauss-Seidel/Jacobi
+ * convergence factors of the discrete Laplacian.
+ */
+#include <stddef.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include "oracle.h"
+
+#define MAXD 3
+#define MAXP 343 /* (2*3+1)^3: radius up to 3 in 3D */
+
+/* Canonical offset list.  Returns P, or a negative value on bad input.  The
+ * offsets are written as P rows of MAXD ints: row q holds (d0, d1, d2) padded
+ * with zeros on the right for ndim < 3. */
+static int canonical_offsets(int ndim, int shape, int npts, int *r_out, int offs[][MAXD])
+{
+    if (ndim < 1 || ndim > MAXD) return -1;
+    int r = -1;
+    for (int cand = 1; cand <= 3; ++cand) {
+        int p = 1;
+        if (shape == ORACLE_STAR) p = 2 * ndim * cand + 1;
+        else if (shape == ORACLE_BOX) { for (int a = 0; a < ndim; ++a) p *= 2 * cand + 1; }
+        else return -1;
+        if (p == npts) { r = cand; break; }
+    }
+    if (r < 0) return -2;
+    int side = 2 * r + 1, total = 1;
+    for (int a = 0; a < ndim; ++a) total *= side;
+    int P = 0;
+    /* enumerate {-r..r}^ndim lexicographically, axis 0 most significant */
+    for (int lin = 0; lin < total; ++lin) {
+        int d[MAXD] = {0, 0, 0};
+        int rem = lin, nonzero = 0;
+        for (int a = ndim - 1; a >= 0; --a) {
+            d[a] = rem % side - r;
+            rem /= side;
+            if (d[a] != 0) ++nonzero;
+        }
+        if (shape == ORACLE_STAR && nonzero > 1) continue;
+        for (int a = 0; a < MAXD; ++a) offs[P][a] = d[a];
+        ++P;
+    }
+    *r_out = r;
+    return P;
+}
+
+int oracle_offsets(int ndim, int shape, int npoints, int *offsets_out)
+{
+    int offs[MAXP][MAXD];
+    int r = 0;
+    int P = canonical_offsets(ndim, shape, npoints, &r, offs);
+    if (P < 0) return P;
+    for (int q = 0; q < P; ++q)
+        for (int a = 0; a < ndim; ++a) offsets_out[q * ndim + a] = offs[q][a];
+    return P;
+}
+
+/* Periodic index: |i| stays within one extent of the range because r < n. */
+static int64_t wrap(int64_t i, int64_t n)
+{
+    if (i < 0) return i + n;
+    if (i >= n) return i - n;
+    return i;
+}
+
+/* Shared argument checks; fills the padded 3-axis extents. */
+static int prepare(int ndim, const int64_t *dims, int shape, int npts, int dependence,
+                   int boundary, int64_t T, int *r, int offs[][MAXD], int64_t n[MAXD])
+{
+    if (!dims || T < 0) return -1;
+    if (dependence != ORACLE_JACOBI && dependence != ORACLE_GAUSS_SEIDEL) return -1;
+    if (boundary != ORACLE_DIRICHLET && boundary != ORACLE_PERIODIC) return -1;
+    int P = canonical_offsets(ndim, shape, npts, r, offs);
+    if (P < 0) return P;
+    for (int a = 0; a < MAXD; ++a) n[a] = 1;
+    for (int a = 0; a < ndim; ++a) {
+        if (dims[a] < 2 * (int64_t)(*r) + 1) return -3;
+        n[a] = dims[a];
+    }
+    return P;
+}
+
+/*
+ * The sweep, written once as a macro over the scalar type so that the FP64
+ * and FP32 variants are textually identical.  The grid is viewed as 3D with
+ * leading unit axes for ndim < 3; a unit axis has a single index and a zero
+ * offset component, which leaves the lexicographic order unchanged.
+ */
+#define DEFINE_SWEEP(NAME, REAL)                                                          \
+int NAME(int ndim, const int64_t *dims, int shape, int npoints, int dependence,           \
+         int boundary, const REAL *coeffs, int64_t T, REAL *grid)                         \
+{                                                                                         \
+    int r = 0;                                                                            \
+    int offs[MAXP][MAXD];                                                                 \
+    int64_t n[MAXD];                                                                      \
+    if (!coeffs || !grid) return -1;                                                      \
+    int P = prepare(ndim, dims, shape, npoints, dependence, boundary, T, &r, offs, n);   \
+    if (P < 0) return P;                                                                  \
+    if (dependence == ORACLE_GAUSS_SEIDEL && boundary == ORACLE_PERIODIC) return -4;      \
+    /* place the real axes last: axis a of the problem is axis (MAXD-ndim+a) here */      \
+    int64_t ext[MAXD];                                                                    \
+    int o[MAXP][MAXD];                                                                    \
+    for (int a = 0; a < MAXD; ++a) ext[a] = 1;                                            \
+    for (int a = 0; a < ndim; ++a) ext[MAXD - ndim + a] = n[a];                           \
+    for (int q = 0; q < P; ++q) {                                                         \
+        for (int a = 0; a < MAXD; ++a) o[q][a] = 0;                                       \
+        for (int a = 0; a < ndim; ++a) o[q][MAXD - ndim + a] = offs[q][a];                \
+    }                                                                                     \
+    int64_t lo[MAXD], hi[MAXD];                                                           \
+    for (int a = 0; a < MAXD; ++a) {                                                      \
+        int real_axis = a >= MAXD - ndim;                                                 \
+        lo[a] = (real_axis && boundary == ORACLE_DIRICHLET) ? r : 0;                      \
+        hi[a] = (real_axis && boundary == ORACLE_DIRICHLET) ? ext[a] - r : ext[a];        \
+    }                                                                                     \
+    int64_t total = ext[0] * ext[1] * ext[2];                                             \
+    REAL *src = grid, *dst = grid, *spare = NULL;                                         \
+    if (dependence == ORACLE_JACOBI) {                                                    \
+        spare = (REAL *)malloc((size_t)total * sizeof(REAL));                             \
+        if (!spare) return -5;                                                            \
+        memcpy(spare, grid, (size_t)total * sizeof(REAL)); /* fixed border values */      \
+        dst = spare;                                                                      \
+    }                                                                                     \
+    /* linear distance of each neighbour (used where no index wraps) */                \
+    int64_t lin[MAXP];                                                                    \
+    for (int q = 0; q < P; ++q)                                                           \
+        lin[q] = ((int64_t)o[q][0] * ext[1] + o[q][1]) * ext[2] + o[q][2];                \
+    for (int64_t t = 0; t < T; ++t) {                                                     \
+        for (int64_t i = lo[0]; i < hi[0]; ++i)                                           \
+            for (int64_t j = lo[1]; j < hi[1]; ++j)                                       \
+                for (int64_t k = lo[2]; k < hi[2]; ++k) {                                 \
+                    int64_t at = (i * ext[1] + j) * ext[2] + k;                           \
+                    REAL acc = 0;                                                         \
+                    for (int q = 0; q < P; ++q) {                                         \
+                        REAL v;                                                           \
+                        if (boundary == ORACLE_DIRICHLET) {                               \
+                            v = src[at + lin[q]];                                         \
+                        } else {                                                          \
+                            int64_t ii = wrap(i + o[q][0], ext[0]);                       \
+                            int64_t jj = wrap(j + o[q][1], ext[1]);                       \
+                            int64_t kk = wrap(k + o[q][2], ext[2]);                       \
+                            v = src[(ii * ext[1] + jj) * ext[2] + kk];                    \
+                        }                                                                 \
+                        REAL term = coeffs[q] * v;                                        \
+                        acc = (q == 0) ? term : acc + term;                               \
+                    }                                                                     \
+                    dst[at] = acc;                                                        \
+                }                                                                         \
+        if (dependence == ORACLE_JACOBI) { REAL *tmp = src; src = dst; dst = tmp; }       \
+    }                                                                                     \
+    if (dependence == ORACLE_JACOBI) {                                                    \
+        if (src != grid) memcpy(grid, src, (size_t)total * sizeof(REAL));                 \
+        free(spare);                                                                      \
+    }                                                                                     \
+    return 0;                                                                             \
+}
+
+DEFINE_SWEEP(oracle_sweep_f64, double)
+DEFINE_SWEEP(oracle_sweep_f32, float)

@@ -1,0 +1,25 @@
+/* Stencil oracle -- test infrastructure only (see oracle.c). */
+#ifndef STENCIL_ORACLE_H
+#define STENCIL_ORACLE_H
+#include <stdint.h>
+
+#define ORACLE_STAR 0
+#define ORACLE_BOX 1
+#define ORACLE_JACOBI 0
+#define ORACLE_GAUSS_SEIDEL 1
+#define ORACLE_DIRICHLET 0
+#define ORACLE_PERIODIC 1
+
+/* Canonical offsets (lexicographic, axis 0 most significant) as npoints rows
+ * of ndim ints.  Returns the number of points, or a negative error code. */
+int oracle_offsets(int ndim, int shape, int npoints, int *offsets_out);
+
+/* T steps of the naive sweep on grid (C order, dims[0] slowest), in place.
+ * Returns 0, or -1 bad argument, -2 point count inconsistent with the shape,
+ * -3 an extent smaller than 2r+1, -4 Gauss-Seidel with periodic boundary,
+ * -5 out of memory. */
+int oracle_sweep_f64(int ndim, const int64_t *dims, int shape, int npoints, int dependence,
+                     int boundary, const double *coeffs, int64_t T, double *grid);
+int oracle_sweep_f32(int ndim, const int64_t *dims, int shape, int npoints, int dependence,
+                     int boundary, const float *coeffs, int64_t T, float *grid);
+#endif

@@ -1,0 +1,208 @@
+"""Seeded synthetic inputs for the stencil workloads.
+
+This module only draws numbers and describes problem shapes; it performs no
+stencil arithmetic.  Both the HIP path (through the tests and the benchmark)
+and the CPU oracle are fed from here, so that they see identical bits.
+
+Problem description (Section 1 of the paper): a time-iterated update of a
+regular d-dimensional grid, classified by dimension, number of points (order),
+shape (star/box), dependence (Jacobi/Gauss-Seidel) and boundary
+(constant/periodic).  ``dims`` are full storage extents; with a constant
+(Dirichlet) boundary the outer layer of width r is part of the array and is
+never written.
+
+Generator: numpy ``Generator(PCG64(seed))``.  FP64 problems draw float64
+values, FP32 problems draw float32 values (the FP64 oracle then runs on those
+same values widened, so that a comparison measures arithmetic error only).
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import Dict, List, Optional, Sequence, Tuple
+
+import numpy as np
+
+STAR, BOX = 0, 1
+JACOBI, GAUSS_SEIDEL = 0, 1
+DIRICHLET, PERIODIC = 0, 1
+F32, F64 = 0, 1
+
+_NP = {F32: np.float32, F64: np.float64}
+
+
+def np_dtype(dtype: int):
+    return _NP[dtype]
+
+
+def npoints(ndim: int, shape: int, radius: int = 1) -> int:
+    """Number of stencil points of a star or box stencil of the given radius."""
+    if shape == STAR:
+        return 2 * ndim * radius + 1
+    return (2 * radius + 1) ** ndim
+
+
+@dataclasses.dataclass
+class Problem:
+    """One stencil problem: everything a caller passes to ``stencil_plan``/``run``."""
+
+    name: str
+    dims: Tuple[int, ...]
+    dtype: int
+    shape: int
+    order: int
+    dependence: int
+    boundary: int
+    coeffs: Tuple[float, ...]
+    T: int
+    seed: int
+    zero_border: bool = False
+
+    @property
+    def ndim(self) -> int:
+        return len(self.dims)
+
+    @property
+    def radius(self) -> int:
+        return 1
+
+    def updated_points(self) -> int:
+        """Points written per step (GStencil/s counts only these)."""
+        if self.boundary == PERIODIC:
+            return int(np.prod(self.dims))
+        return int(np.prod([n - 2 * self.radius for n in self.dims]))
+
+    def with_(self, **kw) -> "Problem":
+        return dataclasses.replace(self, **kw)
+
+
+def uniform_grid(dims: Sequence[int], dtype: int, seed, zero_border: bool = False,
+                 radius: int = 1) -> np.ndarray:
+    """uniform[0,1) values from PCG64(seed), in the storage dtype of the problem.
+
+    ``seed`` may be an int or a tuple of ints (numpy SeedSequence entropy).
+    With ``zero_border`` the outer ``radius`` layers are overwritten with 0.
+    """
+    rng = np.random.Generator(np.random.PCG64(seed))
+    a = rng.random(tuple(int(n) for n in dims), dtype=_NP[dtype])
+    if zero_border:
+        for ax in range(a.ndim):
+            idx = [slice(None)] * a.ndim
+            idx[ax] = slice(0, radius)
+            a[tuple(idx)] = 0
+            idx[ax] = slice(a.shape[ax] - radius, a.shape[ax])
+            a[tuple(idx)] = 0
+    return a
+
+
+def make_grid(p: Problem) -> np.ndarray:
+    return uniform_grid(p.dims, p.dtype, p.seed, p.zero_border)
+
+
+def star_coeffs(ndim: int, centre: float, neighbour: float) -> Tuple[float, ...]:
+    """Coefficients of a radius-1 star stencil in canonical offset order.
+
+    Canonical order lists offsets lexicographically with axis 0 most
+    significant, so the centre sits in the middle: ndim entries before it and
+    ndim after it.
+    """
+    return tuple([neighbour] * ndim + [centre] + [neighbour] * ndim)
+
+
+# ---------------------------------------------------------------------------
+# The workloads.  Sizes, coefficients and step counts are the ones the
+# throughput figures are quoted on; the generator recipe is described above.
+# ---------------------------------------------------------------------------
+
+def heat1d(periodic: bool = False, n: int = 100000, T: int = 1000) -> Problem:
+    """1D 3-point Jacobi, coefficients (1/4, 1/2, 1/4), fixed ends (or periodic)."""
+    return Problem("heat1d_3p" + ("_periodic" if periodic else ""), (n,), F64, STAR, 3,
+                   JACOBI, PERIODIC if periodic else DIRICHLET, (0.25, 0.5, 0.25), T, 1)
+
+
+def box2d9p(dtype: int = F64, n: int = 8192, T: int = 1000) -> Problem:
+    """2D 9-point box Jacobi, all coefficients 1/9, zero Dirichlet border."""
+    return Problem("box2d9p" + ("_f32" if dtype == F32 else ""), (n, n), dtype, BOX, 9,
+                   JACOBI, DIRICHLET, tuple([1.0 / 9.0] * 9), T, 2, zero_border=True)
+
+
+def star3d7p(dtype: int = F64, n: int = 512, T: int = 100) -> Problem:
+    """3D 7-point star Jacobi, centre 0.4, six neighbours 0.1, periodic."""
+    return Problem("star3d7p" + ("_f32" if dtype == F32 else ""), (n, n, n), dtype, STAR, 7,
+                   JACOBI, PERIODIC, star_coeffs(3, 0.4, 0.1), T, 3)
+
+
+def gs2d5p(n: int = 4096, T: int = 100) -> Problem:
+    """2D 5-point Gauss-Seidel in place, all five coefficients 0.2, zero border."""
+    return Problem("gs2d5p", (n, n), F64, STAR, 5, GAUSS_SEIDEL, DIRICHLET,
+                   tuple([0.2] * 5), T, 4, zero_border=True)
+
+
+WORKLOADS = {
+    "heat1d_3p": heat1d,
+    "box2d9p": box2d9p,
+    "star3d7p": star3d7p,
+    "gs2d5p": gs2d5p,
+}
+
+
+# ---------------------------------------------------------------------------
+# Serving mix: a Poisson stream of mixed solves.
+# ---------------------------------------------------------------------------
+
+@dataclasses.dataclass
+class Request:
+    index: int
+    arrival_s: float
+    problem: Problem
+
+
+def _log_uniform_int(rng: np.random.Generator, lo: int, hi: int) -> int:
+    return int(round(math.exp(rng.uniform(math.log(lo), math.log(hi)))))
+
+
+def serving_mix(n_requests: int = 2000, rate_per_s: float = 100.0, seed: int = 5,
+                side2d: Tuple[int, int] = (64, 4096), side3d: Tuple[int, int] = (32, 256),
+                n1d: Tuple[int, int] = (1000, 1000000), steps: Tuple[int, int] = (10, 1000)
+                ) -> List[Request]:
+    """Poisson arrivals of 1D/2D/3D Jacobi and 2D Gauss-Seidel solves.
+
+    Kind is uniform over {1D 3-point Jacobi, 2D Jacobi (5-point star or
+    9-point box, 50/50), 3D 7-point Jacobi, 2D 5-point Gauss-Seidel}; 2D
+    sides are log-uniform in ``side2d``, 3D sides in ``side3d``, 1D lengths in
+    ``n1d``; T is uniform in ``steps``; FP32/FP64 50/50; Jacobi boundaries are
+    Dirichlet/periodic 50/50 and Gauss-Seidel is Dirichlet.  Request ``i``
+    draws its grid from seed ``(seed, i)``.
+    """
+    rng = np.random.Generator(np.random.PCG64(seed))
+    t = 0.0
+    out: List[Request] = []
+    for i in range(n_requests):
+        t += rng.exponential(1.0 / rate_per_s)
+        kind = int(rng.integers(0, 4))
+        dtype = F32 if rng.random() < 0.5 else F64
+        T = int(rng.integers(steps[0], steps[1] + 1))
+        periodic = rng.random() < 0.5
+        bnd = PERIODIC if periodic else DIRICHLET
+        if kind == 0:
+            n = _log_uniform_int(rng, *n1d)
+            p = Problem(f"req{i}_1d3p", (n,), dtype, STAR, 3, JACOBI, bnd, (0.25, 0.5, 0.25), T,
+                        (seed, i))
+        elif kind == 1:
+            ny, nx = _log_uniform_int(rng, *side2d), _log_uniform_int(rng, *side2d)
+            if rng.random() < 0.5:
+                p = Problem(f"req{i}_2d5p", (ny, nx), dtype, STAR, 5, JACOBI, bnd,
+                            tuple([0.2] * 5), T, (seed, i))
+            else:
+                p = Problem(f"req{i}_2d9p", (ny, nx), dtype, BOX, 9, JACOBI, bnd,
+                            tuple([1.0 / 9.0] * 9), T, (seed, i))
+        elif kind == 2:
+            s = [_log_uniform_int(rng, *side3d) for _ in range(3)]
+            p = Problem(f"req{i}_3d7p", tuple(s), dtype, STAR, 7, JACOBI, bnd,
+                        star_coeffs(3, 0.4, 0.1), T, (seed, i))
+        else:
+            ny, nx = _log_uniform_int(rng, *side2d), _log_uniform_int(rng, *side2d)
+            p = Problem(f"req{i}_gs2d5p", (ny, nx), dtype, STAR, 5, GAUSS_SEIDEL, DIRICHLET,
+                        tuple([0.2] * 5), T, (seed, i))
+        out.append(Request(i, t, p))
+    return out
