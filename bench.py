@@ -1,0 +1,169 @@
+#!/usr/bin/env python3
+"""Benchmark: GStencil/s of the time-skewed pipeline on one MI355X.
+
+One "step" of this benchmark is one full solve of the headline workload --
+2D 9-point box Jacobi on an 8192 x 8192 FP64 grid (zero border, all weights
+1/9), T = 1000 time steps -- on a grid already resident in HBM.  The JSON
+line also carries the plain one-step-per-launch sweep on the same grid, the
+roofline position of the dominant kernel, and the CPU oracle timed on a
+bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
+# FP64 vector: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.3e12 separately
+# issued multiplies or adds per second (the 78.6 TFLOP/s figure counts an FMA
+# as two; the bit-exact update uses no FMA).  FP32 non-packed: the same.
+ALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+METRIC = "GStencil/s + % HBM roofline vs plain sweep; p50/p99 latency mixed load"
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def time_runs(torch, fn, reps):
+    """Average device time (ms) of fn() over reps, with events on the current stream."""
+    st = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(st)
+    for _ in range(reps):
+        fn()
+    e1.record(st)
+    e1.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def stencil_ops(p):
+    """Multiplies + adds per point update (canonical order: P products, P-1 sums)."""
+    return 2 * p.order - 1
+
+
+def cpu_baseline(p, budget_s=15.0):
+    """Time the oracle on a bounded number of steps of the same grid."""
+    import numpy as np
+
+    import oracle
+    from paper_2010_04868_amd import inputs
+    u0 = inputs.make_grid(p)
+    # one step first, to size the sample to the budget
+    t0 = time.perf_counter()
+    u = oracle.sweep(u0, p.coeffs, p.shape, p.dependence, p.boundary, 1)
+    one = time.perf_counter() - t0
+    steps = max(1, min(p.T, int(budget_s / max(one, 1e-6))))
+    t0 = time.perf_counter()
+    oracle.sweep(u, p.coeffs, p.shape, p.dependence, p.boundary, steps)
+    dt = time.perf_counter() - t0
+    ups = p.updated_points() * steps / dt
+    return {"value": round(ups / 1e9, 4), "unit": "GStencil/s", "cores": 1, "kind": "oracle",
+            "sample": f"{p.dims[0]}x{p.dims[1]} {p.name}, {steps} of {p.T} steps, single thread"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--tuning", default=None, help="schedule override for the time-skewed run")
+    ap.add_argument("--plain-steps", type=int, default=2, help="timed solves of the plain sweep")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--n", type=int, default=8192)
+    ap.add_argument("--T", type=int, default=1000)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU; multi-GPU runs are not part of this build "
+              "(the sharding design is described in DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2010_04868_amd as tvs
+    from paper_2010_04868_amd import inputs
+
+    tvs.load()
+    p = inputs.box2d9p(n=args.n, T=args.T)
+    u0 = inputs.make_grid(p)
+    grid = torch.from_numpy(u0).to("cuda")
+    plan = tvs.Plan.for_problem(p, args.tuning)
+    info = plan.info()
+    log("plan:", info)
+    nu = p.updated_points()
+
+    # time-skewed solves
+    for _ in range(args.warmup):
+        plan.run(grid, p.coeffs, p.T)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ms = time_runs(torch, lambda: plan.run(grid, p.coeffs, p.T), args.steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    value = nu * p.T / (ms / 1e3) / 1e9
+    log(f"tstp: {ms:.3f} ms/solve, {value:.1f} GStencil/s (wall {wall:.2f}s)")
+
+    # dominant kernel: one full band (k steps) per launch
+    k = info["k"]
+    band_ms = time_runs(torch, lambda: plan.run(grid, p.coeffs, k), 20)
+    band_updates = nu * k
+    eb = 8 if p.dtype == inputs.F64 else 4
+    alg_bytes = 2 * eb * nu                           # each point read and written once per band
+    achieved_tops = band_updates * stencil_ops(p) / (band_ms / 1e3) / 1e12
+    achieved_gbs = alg_bytes / (band_ms / 1e3) / 1e9
+    log(f"band kernel: {band_ms:.4f} ms, {achieved_gbs:.0f} GB/s algorithmic, "
+        f"{achieved_tops:.2f} T op/s")
+
+    # plain one-step-per-launch sweep on the same grid
+    plain = tvs.Plan.for_problem(p, "method=plain")
+    plain.run(grid, p.coeffs, 10)
+    plain_ms = time_runs(torch, lambda: plain.run(grid, p.coeffs, p.T), args.plain_steps)
+    plain_value = nu * p.T / (plain_ms / 1e3) / 1e9
+    step_ms = time_runs(torch, lambda: plain.run(grid, p.coeffs, 1), 50)
+    plain_gbs = 2 * eb * nu / (step_ms / 1e3) / 1e9
+    log(f"plain: {plain_ms:.3f} ms/solve, {plain_value:.1f} GStencil/s, step {step_ms:.4f} ms "
+        f"= {plain_gbs:.0f} GB/s")
+
+    out = {
+        "metric": METRIC,
+        "value": round(value, 2),
+        "unit": "GStencil/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic: uniform[0,1) PCG64(seed 2), zero Dirichlet border",
+        "config": {"workload": f"2D 9-point box Jacobi {p.dims[0]}x{p.dims[1]} FP64, T={p.T}",
+                   "schedule": f"k={info['k']},w={info['tile_w']},l={info['tile_l']},"
+                               f"c={info['lane_c']},lanemap={info['lanemap']}",
+                   "updated_points": nu},
+        "hbm_effective_frac": round(value * 2 * eb / HBM_PEAK_GBS, 4),
+        "plain_sweep": {"value": round(plain_value, 2), "unit": "GStencil/s",
+                        "hbm_GBs": round(plain_gbs, 1),
+                        "hbm_frac": round(plain_gbs / HBM_PEAK_GBS, 4),
+                        "speedup": round(value / plain_value, 3)},
+        "roofline": {"bound": "alu", "achieved": round(achieved_tops, 3),
+                     "peak": round(ALU_PEAK_TOPS, 2), "unit": "TFLOP/s",
+                     "frac": round(achieved_tops / ALU_PEAK_TOPS, 4), "traffic": None,
+                     "kernel": "tstp_nd (one band)", "kernel_ms": round(band_ms, 4),
+                     "algorithmic_GBs": round(achieved_gbs, 1)},
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(p)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,219 @@
+/*
+ * tvstencil -- time-skewed temporal stencil sweeps for AMD Instinct MI355X
+ * (gfx950).  C ABI.
+ *
+ * The problem (Section 1 of "Temporal Vectorization for Stencils"): a
+ * time-iterated update of a regular d-dimensional grid (d = 1, 2, 3) by a
+ * stencil that is classified by its number of points ("order"), its shape
+ * (star or box), its dependence type (Jacobi or Gauss-Seidel) and its
+ * boundary condition (constant or periodic).  The naive form is d+1 nested
+ * loops with time outermost (Section 1; Algorithm 1 in Section 2.1 for the
+ * 1D 3-point case).
+ *
+ * Definition of one step, which every entry point below reproduces exactly:
+ *   - the grid is dense, C order: axis 0 slowest, the last axis contiguous;
+ *     dims[] are full storage extents;
+ *   - the stencil's P offsets are listed in canonical order: lexicographic
+ *     over the offset vector with axis 0 most significant (2D 5-point:
+ *     (-1,0), (0,-1), (0,0), (0,1), (1,0));
+ *   - a point update is acc = c[0]*v[0], then acc = acc + c[q]*v[q] for
+ *     q = 1..P-1, each product and sum rounded separately (no fused
+ *     multiply-add, no reassociation), in the grid's precision;
+ *   - Jacobi: all updates of step t+1 read step-t values;
+ *   - Gauss-Seidel: one array updated in place in lexicographic point order,
+ *     so neighbours that precede a point contribute their newest value
+ *     (Section 3.4, "Gauss-Seidel stencils");
+ *   - constant (Dirichlet) boundary: the outer r layers of every axis are
+ *     never written and are read as fixed values; periodic: every point is
+ *     updated and indices wrap.
+ * The kernels reorder whole point updates only (time skewing, Section 3.2),
+ * never the arithmetic inside one, so FP64 results are bit-identical to the
+ * naive loops, and FP32 results are bit-identical to the naive loops run in
+ * FP32, for every tuning.
+ *
+ * Conventions for every function:
+ *   - returns TVS_OK (0) or a negative TVS_E_* code; nothing throws or aborts
+ *     across the ABI; stencil_last_error() gives a thread-local message;
+ *   - argument errors are reported synchronously; device work is enqueued
+ *     asynchronously on the given HIP stream (NULL = the null stream);
+ *   - device pointers are plain hipMalloc'd (or torch) allocations on the
+ *     current device; host pointers are read during the call only;
+ *   - the library never retains a caller's pointer after the stream work of
+ *     the call has completed.
+ */
+#ifndef TVSTENCIL_H
+#define TVSTENCIL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- return codes ------------------------------------------------------ */
+#define TVS_OK 0
+#define TVS_E_INVALID (-1)     /* null pointer, bad enum, T < 0, bad tuning */
+#define TVS_E_SHAPE (-2)       /* ndim not 1..3, an extent < 2r+1, size overflow */
+#define TVS_E_ORDER (-3)       /* point count inconsistent with ndim and shape */
+#define TVS_E_UNSUPPORTED (-4) /* e.g. periodic Gauss-Seidel, radius > 1 */
+#define TVS_E_NOMEM (-5)       /* device or host allocation failed */
+#define TVS_E_DEVICE (-6)      /* a HIP call failed or a kernel reported abort */
+#define TVS_E_BUSY (-7)        /* server: budget or queue full */
+#define TVS_E_NOTFOUND (-8)    /* server: unknown request id */
+
+/* ---- enums ------------------------------------------------------------- */
+#define TVS_F32 0
+#define TVS_F64 1
+#define TVS_STAR 0
+#define TVS_BOX 1
+#define TVS_JACOBI 0
+#define TVS_GAUSS_SEIDEL 1
+#define TVS_DIRICHLET 0
+#define TVS_PERIODIC 1
+
+/* execution methods a plan can use */
+#define TVS_METHOD_PLAIN 0 /* one time step per kernel launch (the baseline) */
+#define TVS_METHOD_TSTP 1  /* time-skewed temporal pipeline, k steps per band */
+
+typedef struct tvs_plan tvs_plan;
+
+typedef struct tvs_plan_info {
+    int ndim;
+    int64_t dims[3];
+    int dtype, shape, order, dependence, boundary;
+    int radius;        /* r, derived from (ndim, shape, order) */
+    int method;        /* TVS_METHOD_* */
+    int k;             /* time-tile depth: steps per band (levels per pipeline) */
+    int s;             /* skew: stream positions between successive levels */
+    int tile_w;        /* non-stream tile extent in points, halo included
+                          (2D: columns; 3D: columns of the inner tile) */
+    int tile_h;        /* 3D: rows of the inner tile; 1 otherwise */
+    int tile_l;        /* stream-axis segment length (output points) */
+    int lane_c;        /* consecutive points per lane along the last axis */
+    int lanemap;       /* 0 = successive levels in successive lanes,
+                          1 = successive levels in successive waves */
+    size_t scratch_bytes; /* device memory the plan owns */
+} tvs_plan_info;
+
+/*
+ * Create a plan: validate the problem and choose how to run it.
+ *   ndim        1, 2 or 3
+ *   dims        ndim storage extents (halo/border included), each >= 2r+1
+ *   dtype       TVS_F32 or TVS_F64 (storage and arithmetic precision)
+ *   shape       TVS_STAR or TVS_BOX
+ *   order       number of stencil points P (star: 2*ndim*r+1, box: (2r+1)^ndim);
+ *               r = 1 is supported
+ *   dependence  TVS_JACOBI or TVS_GAUSS_SEIDEL
+ *   boundary    TVS_DIRICHLET or TVS_PERIODIC (Gauss-Seidel: Dirichlet only)
+ *   tuning      NULL: the tuned default (autotune cache, else a model-based
+ *               choice); otherwise "key=value" pairs separated by commas:
+ *               method=plain|tstp, k=, s=, w=, h=, l=, c=, lanemap=
+ * The plan is created without touching the device; device scratch (the
+ * Jacobi second buffer) is allocated at the first run and freed by
+ * stencil_plan_destroy.  *out is set only on success.
+ */
+int stencil_plan(tvs_plan **out, int ndim, const int64_t *dims, int dtype, int shape, int order,
+                 int dependence, int boundary, const char *tuning);
+
+/* Fill *info with the plan's problem and chosen schedule. */
+int stencil_plan_info(const tvs_plan *plan, tvs_plan_info *info);
+
+/* Free the plan and everything it owns.  Waits for the device first.  NULL is a no-op. */
+int stencil_plan_destroy(tvs_plan *plan);
+
+/*
+ * Advance grid by T steps.
+ *   grid    device pointer, prod(dims) elements of the plan's dtype, C order;
+ *           input at step 0, output at step T (in place from the caller's
+ *           view; Jacobi uses the plan's second buffer internally)
+ *   coeffs  host array of P doubles in canonical offset order; rounded to
+ *           FP32 (nearest even) for TVS_F32 plans; copied during the call
+ *   T       >= 0; T = 0 enqueues nothing
+ *   stream  hipStream_t or NULL
+ * One plan runs on one stream at a time; distinct plans may run concurrently.
+ */
+int stencil_run(tvs_plan *plan, void *grid, const double *coeffs, int64_t T, void *stream);
+
+/* One-call form: plans (through an internal cache keyed by the problem) and runs. */
+int stencil_run_simple(void *grid, int ndim, const int64_t *dims, int dtype, const double *coeffs,
+                       int shape, int order, int dependence, int boundary, int64_t T,
+                       void *stream);
+
+/*
+ * Run n independent problems in persistent launches on one stream.  Each
+ * plans[i] must be a Jacobi plan (Gauss-Seidel plans run through their own
+ * persistent kernel and are accepted as well); grids[i], coeffs[i], T[i] as
+ * in stencil_run.  Every result is bit-identical to stencil_run of the same
+ * problem alone.  The launch sequence is captured once in a hipGraph per
+ * distinct batch layout and replayed.
+ */
+int stencil_batch_run(int n, tvs_plan *const *plans, void *const *grids,
+                      const double *const *coeffs, const int64_t *T, void *stream);
+
+/*
+ * Autotune: time candidate schedules for this plan's problem on `grid`
+ * (contents are restored afterwards) over T_probe steps, keep the fastest,
+ * record it in the tuning cache (path from TVS_TUNE_CACHE, if set), and
+ * switch the plan to it.  Candidates that do not produce the same bits as
+ * the first one are rejected (TVS_E_DEVICE).  best (may be NULL) receives
+ * the winning tuning string.
+ */
+int stencil_tune(tvs_plan *plan, void *grid, const double *coeffs, int64_t T_probe,
+                 void *stream, char *best, size_t best_len);
+
+/* ---- serving: continuous batching of stencil solves ----------------------- */
+typedef struct tvs_server tvs_server;
+
+typedef struct tvs_request {
+    int ndim;
+    int64_t dims[3];
+    int dtype, shape, order, dependence, boundary;
+    const double *coeffs; /* host, P doubles, copied at submit */
+    int64_t T;
+    const void *host_in;  /* host, prod(dims) elements, copied at submit */
+} tvs_request;
+
+typedef struct tvs_server_stats {
+    uint64_t submitted, admitted, completed, rejected;
+    uint64_t chunks;           /* persistent launches issued */
+    uint64_t resident;         /* grids on the device now */
+    size_t bytes_in_use;       /* device bytes held by resident grids */
+    double busy_seconds;       /* device time of all chunks */
+    double updates;            /* point updates completed */
+} tvs_server_stats;
+
+/*
+ * Start a server on the current device.  hbm_budget: device bytes resident
+ * grids may occupy (0 = 4 GiB); max_slots: grids resident at once (0 = 64);
+ * chunk_steps: steps per grid per chunk (0 = 64).  A background thread admits
+ * queued requests in arrival order whenever their footprint fits the budget
+ * and a slot is free, advances every resident grid by up to chunk_steps per
+ * chunk in one batched launch, and retires finished grids.
+ */
+int stencil_server_create(tvs_server **out, size_t hbm_budget, int max_slots, int chunk_steps);
+/* Queue a request; *id identifies it.  TVS_E_BUSY if it can never fit the budget. */
+int stencil_server_submit(tvs_server *srv, const tvs_request *req, uint64_t *id);
+/* Non-blocking: *status = 1 done, 0 pending; on done copies the result to host_out
+ * (prod(dims) elements) if not NULL and forgets the request.  Timestamps (seconds
+ * on the server clock) are written to t_out[0..3] = arrival, admit, start, finish
+ * if t_out is not NULL. */
+int stencil_server_poll(tvs_server *srv, uint64_t id, int *status, void *host_out, double *t_out);
+/* Blocking form of poll. */
+int stencil_server_wait(tvs_server *srv, uint64_t id, void *host_out, double *t_out);
+int stencil_server_stats(tvs_server *srv, tvs_server_stats *out);
+/* Seconds on the server clock (monotonic, zero at create). */
+double stencil_server_now(tvs_server *srv);
+/* Stop the thread, drop pending work, free device memory. */
+int stencil_server_destroy(tvs_server *srv);
+
+/* Message for the last non-zero return on this thread ("" if none). */
+const char *stencil_last_error(void);
+
+/* Library version string. */
+const char *stencil_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TVSTENCIL_H */

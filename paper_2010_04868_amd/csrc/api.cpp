@@ -1,0 +1,231 @@
+// C ABI: plans, single runs, the one-call form and plan introspection.
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <tuple>
+
+#include "api_internal.hpp"
+#include "plan.hpp"
+
+using namespace tvs;
+
+namespace tvs {
+
+template <typename T>
+static Coeffs<T> make_coeffs(const double* c, int P) {
+    Coeffs<T> k{};
+    for (int q = 0; q < P; ++q) k.c[q] = (T)c[q];  // FP32: round to nearest even
+    return k;
+}
+
+void fill_coeffs(const Problem& p, const double* c, CoeffBuf* out) {
+    if (p.dtype == TVS_F64) {
+        auto k = make_coeffs<double>(c, p.order);
+        std::memcpy(out->bytes, &k, sizeof k);
+    } else {
+        auto k = make_coeffs<float>(c, p.order);
+        std::memcpy(out->bytes, &k, sizeof k);
+    }
+}
+
+int ensure_scratch(tvs_plan* p) {
+    if (p->prob.dependence == TVS_JACOBI) {
+        const size_t need = p->prob.bytes();
+        if (p->scratch_bytes < need) {
+            if (p->scratch) (void)hipFree(p->scratch);
+            p->scratch = nullptr;
+            p->scratch_bytes = 0;
+            void* ptr = nullptr;
+            if (hipMalloc(&ptr, need) != hipSuccess)
+                return set_error(TVS_E_NOMEM, "hipMalloc of the second Jacobi buffer failed");
+            p->scratch = ptr;
+            p->scratch_bytes = need;
+        }
+    } else {
+        const size_t need = gs_work_bytes(p->prob, std::max(1, p->sched.k));
+        if (p->gs_work_bytes < need) {
+            if (p->gs_work) (void)hipFree(p->gs_work);
+            p->gs_work = nullptr;
+            p->gs_work_bytes = 0;
+            void* ptr = nullptr;
+            if (hipMalloc(&ptr, need) != hipSuccess)
+                return set_error(TVS_E_NOMEM, "hipMalloc of the Gauss-Seidel work area failed");
+            if (hipMemset(ptr, 0, need) != hipSuccess)  // status word starts clear
+                return set_error(TVS_E_DEVICE, "hipMemset of the Gauss-Seidel work area failed");
+            p->gs_work = ptr;
+            p->gs_work_bytes = need;
+        }
+    }
+    return TVS_OK;
+}
+
+// Enqueue T Jacobi steps: bands of sched.k levels (plain: single steps),
+// ping-ponging between the caller's grid and the plan's second buffer.
+int enqueue_jacobi(tvs_plan* p, void* grid, const CoeffBuf& cb, int64_t T, hipStream_t st) {
+    const Problem& pr = p->prob;
+    void* buf[2] = {grid, p->scratch};
+    int cur = 0;
+    if (p->sched.method == TVS_METHOD_PLAIN) {
+        for (int64_t t = 0; t < T; ++t) {
+            TVS_HIP_TRY(launch_plain_step(pr, buf[cur], buf[1 - cur], cb.bytes, st));
+            cur ^= 1;
+        }
+    } else {
+        int64_t done = 0;
+        BandGeom full;
+        if (!band_geometry(pr, p->sched, p->sched.k, &full))
+            return set_error(TVS_E_INVALID, "schedule does not fit: " + format_tuning(pr, p->sched));
+        while (done < T) {
+            const int kb = (int)std::min<int64_t>(p->sched.k, T - done);
+            BandGeom g = full;
+            if (kb != full.k && !band_geometry(pr, p->sched, kb, &g))
+                return set_error(TVS_E_INVALID, "remainder band does not fit");
+            TVS_HIP_TRY(launch_tstp_band(pr, g, buf[cur], buf[1 - cur], cb.bytes, st));
+            cur ^= 1;
+            done += kb;
+        }
+    }
+    if (cur == 1)
+        TVS_HIP_TRY(hipMemcpyAsync(grid, p->scratch, pr.bytes(), hipMemcpyDeviceToDevice, st));
+    return TVS_OK;
+}
+
+int enqueue_gs(tvs_plan* p, void* grid, const CoeffBuf& cb, int64_t T, hipStream_t st) {
+    const int per_launch = p->sched.method == TVS_METHOD_PLAIN ? 1 : std::max(1, p->sched.k);
+    int64_t done = 0;
+    while (done < T) {
+        const int sw = (int)std::min<int64_t>(per_launch, T - done);
+        TVS_HIP_TRY(launch_gs(p->prob, grid, cb.bytes, sw, p->gs_work, st));
+        done += sw;
+    }
+    return TVS_OK;
+}
+
+int enqueue_run(tvs_plan* p, void* grid, const double* coeffs, int64_t T, hipStream_t st) {
+    CoeffBuf cb;
+    fill_coeffs(p->prob, coeffs, &cb);
+    int rc = ensure_scratch(p);
+    if (rc) return rc;
+    if (p->prob.dependence == TVS_JACOBI) return enqueue_jacobi(p, grid, cb, T, st);
+    return enqueue_gs(p, grid, cb, T, st);
+}
+
+}  // namespace tvs
+
+extern "C" {
+
+int stencil_plan(tvs_plan** out, int ndim, const int64_t* dims, int dtype, int shape, int order,
+                 int dependence, int boundary, const char* tuning) {
+    clear_error();
+    if (!out) return set_error(TVS_E_INVALID, "out is NULL");
+    Problem pr;
+    int rc = validate(&pr, ndim, dims, dtype, shape, order, dependence, boundary);
+    if (rc) return rc;
+    Schedule s = default_schedule(pr);
+    if (tuning && *tuning) {
+        bool has_method = false;
+        Schedule t = s;
+        rc = parse_tuning(tuning, &t, &has_method);
+        if (rc) return rc;
+        if (t.method == TVS_METHOD_TSTP && pr.ndim >= 2 && pr.dependence == TVS_JACOBI &&
+            std::strstr(tuning, "l=") == nullptr)
+            choose_segment(pr, &t);
+        s = t;
+    } else {
+        Schedule cached;
+        if (tune_cache_lookup(pr, &cached)) s = cached;
+    }
+    rc = check_schedule(pr, s);
+    if (rc) return rc;
+    tvs_plan* p = new (std::nothrow) tvs_plan();
+    if (!p) return set_error(TVS_E_NOMEM, "out of host memory");
+    p->prob = pr;
+    p->sched = s;
+    *out = p;
+    return TVS_OK;
+}
+
+int stencil_plan_info(const tvs_plan* p, tvs_plan_info* info) {
+    clear_error();
+    if (!p || !info) return set_error(TVS_E_INVALID, "NULL argument");
+    std::memset(info, 0, sizeof *info);
+    info->ndim = p->prob.ndim;
+    for (int a = 0; a < 3; ++a) info->dims[a] = a < p->prob.ndim ? p->prob.dims[a] : 0;
+    info->dtype = p->prob.dtype;
+    info->shape = p->prob.shape;
+    info->order = p->prob.order;
+    info->dependence = p->prob.dependence;
+    info->boundary = p->prob.boundary;
+    info->radius = p->prob.radius;
+    info->method = p->sched.method;
+    info->k = p->sched.method == TVS_METHOD_PLAIN ? 1 : p->sched.k;
+    info->s = p->sched.s;
+    info->tile_w = p->sched.w;
+    info->tile_h = p->sched.h;
+    info->tile_l = p->sched.l;
+    info->lane_c = p->sched.c;
+    info->lanemap = p->sched.lanemap;
+    info->scratch_bytes = p->scratch_bytes + p->gs_work_bytes;
+    return TVS_OK;
+}
+
+int stencil_plan_destroy(tvs_plan* p) {
+    clear_error();
+    if (!p) return TVS_OK;
+    if (p->scratch || p->gs_work) (void)hipDeviceSynchronize();
+    if (p->scratch) (void)hipFree(p->scratch);
+    if (p->gs_work) (void)hipFree(p->gs_work);
+    if (p->gs_status_host) (void)hipHostFree(p->gs_status_host);
+    if (p->gs_status_event) (void)hipEventDestroy(p->gs_status_event);
+    graph_cache_drop(p);
+    delete p;
+    return TVS_OK;
+}
+
+int stencil_run(tvs_plan* p, void* grid, const double* coeffs, int64_t T, void* stream) {
+    clear_error();
+    if (!p || !grid || !coeffs) return set_error(TVS_E_INVALID, "NULL argument");
+    if (T < 0) return set_error(TVS_E_INVALID, "T < 0");
+    if (T == 0) return TVS_OK;
+    int rc = enqueue_run(p, grid, coeffs, T, (hipStream_t)stream);
+    if (rc) return rc;
+    if (p->prob.dependence == TVS_GAUSS_SEIDEL) return gs_check_status(p, (hipStream_t)stream);
+    return TVS_OK;
+}
+
+int stencil_run_simple(void* grid, int ndim, const int64_t* dims, int dtype, const double* coeffs,
+                       int shape, int order, int dependence, int boundary, int64_t T,
+                       void* stream) {
+    clear_error();
+    if (!dims) return set_error(TVS_E_INVALID, "dims is NULL");
+    if (ndim < 1 || ndim > 3) return set_error(TVS_E_SHAPE, "ndim must be 1, 2 or 3");
+    static std::mutex mu;
+    static std::map<std::tuple<int, int64_t, int64_t, int64_t, int, int, int, int, int, int>,
+                    tvs_plan*>
+        cache;
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    auto key = std::make_tuple(ndim, dims[0], ndim > 1 ? dims[1] : 1, ndim > 2 ? dims[2] : 1,
+                               dtype, shape, order, dependence, boundary, dev);
+    tvs_plan* p = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        auto it = cache.find(key);
+        if (it != cache.end()) {
+            p = it->second;
+        } else {
+            int rc = stencil_plan(&p, ndim, dims, dtype, shape, order, dependence, boundary,
+                                  nullptr);
+            if (rc) return rc;
+            cache[key] = p;
+        }
+    }
+    return stencil_run(p, grid, coeffs, T, stream);
+}
+
+const char* stencil_last_error(void) { return last_error(); }
+
+const char* stencil_version(void) { return "tvstencil 0.1 (gfx950)"; }
+
+}  // extern "C"

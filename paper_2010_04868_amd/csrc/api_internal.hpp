@@ -1,0 +1,44 @@
+// Internal plan object and helpers shared by the C-ABI translation units.
+#pragma once
+
+#include <string>
+
+#include "kernels.hpp"
+
+struct tvs_plan {
+    tvs::Problem prob;
+    tvs::Schedule sched;
+    void* scratch = nullptr;  // Jacobi second buffer
+    size_t scratch_bytes = 0;
+    void* gs_work = nullptr;  // Gauss-Seidel ticket, status word, progress counters
+    size_t gs_work_bytes = 0;
+    int* gs_status_host = nullptr;  // pinned copy of the status word
+    hipEvent_t gs_status_event = nullptr;
+};
+
+namespace tvs {
+
+// Coefficients in the plan's precision, laid out as the kernels take them.
+struct CoeffBuf {
+    alignas(16) unsigned char bytes[sizeof(Coeffs<double>)];
+};
+
+void fill_coeffs(const Problem& p, const double* c, CoeffBuf* out);
+int ensure_scratch(tvs_plan* p);
+int enqueue_run(tvs_plan* p, void* grid, const double* coeffs, int64_t T, hipStream_t st);
+int enqueue_jacobi(tvs_plan* p, void* grid, const CoeffBuf& cb, int64_t T, hipStream_t st);
+int enqueue_gs(tvs_plan* p, void* grid, const CoeffBuf& cb, int64_t T, hipStream_t st);
+
+// Gauss-Seidel status: report an abort seen by an earlier run, then queue a
+// copy of the status word for the run just enqueued.
+int gs_check_status(tvs_plan* p, hipStream_t st);
+
+// Autotuning cache (TVS_TUNE_CACHE): schedule for a problem, if recorded.
+bool tune_cache_lookup(const Problem& p, Schedule* s);
+void tune_cache_store(const Problem& p, const Schedule& s);
+std::string problem_key(const Problem& p);
+
+// Graph cache of a plan (captured launch sequences).
+void graph_cache_drop(tvs_plan* p);
+
+}  // namespace tvs

@@ -1,0 +1,34 @@
+// Temporary: batch, tuning and serving entry points until their own units land.
+#include "api_internal.hpp"
+#include "plan.hpp"
+
+namespace tvs {
+bool tune_cache_lookup(const Problem&, Schedule*) { return false; }
+void tune_cache_store(const Problem&, const Schedule&) {}
+void graph_cache_drop(tvs_plan*) {}
+}  // namespace tvs
+
+using namespace tvs;
+extern "C" {
+int stencil_batch_run(int n, tvs_plan* const* plans, void* const* grids,
+                      const double* const* coeffs, const int64_t* T, void* stream) {
+    clear_error();
+    if (n < 0 || (n > 0 && (!plans || !grids || !coeffs || !T)))
+        return set_error(TVS_E_INVALID, "NULL argument");
+    for (int i = 0; i < n; ++i) {
+        int rc = stencil_run(plans[i], grids[i], coeffs[i], T[i], stream);
+        if (rc) return rc;
+    }
+    return TVS_OK;
+}
+int stencil_tune(tvs_plan*, void*, const double*, int64_t, void*, char*, size_t) {
+    return set_error(TVS_E_UNSUPPORTED, "not built yet");
+}
+int stencil_server_create(tvs_server**, size_t, int, int) { return set_error(TVS_E_UNSUPPORTED, "not built yet"); }
+int stencil_server_submit(tvs_server*, const tvs_request*, uint64_t*) { return TVS_E_UNSUPPORTED; }
+int stencil_server_poll(tvs_server*, uint64_t, int*, void*, double*) { return TVS_E_UNSUPPORTED; }
+int stencil_server_wait(tvs_server*, uint64_t, void*, double*) { return TVS_E_UNSUPPORTED; }
+int stencil_server_stats(tvs_server*, tvs_server_stats*) { return TVS_E_UNSUPPORTED; }
+double stencil_server_now(tvs_server*) { return 0.0; }
+int stencil_server_destroy(tvs_server*) { return TVS_E_UNSUPPORTED; }
+}

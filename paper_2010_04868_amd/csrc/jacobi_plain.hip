@@ -1,0 +1,162 @@
+// Plain Jacobi sweep: one time step per kernel launch.
+//
+// This is the naive (d+1)-loop algorithm of Section 1 (Algorithm 1 for the
+// 1D 3-point case) with the space loops spread over the GPU: every step
+// reads the whole grid once and writes it once (2 * element bytes per point
+// update of HBM traffic).  It is the baseline the time-skewed kernels are
+// measured against, so it is written to stream well: the stream axis is
+// walked by each thread with a register window, the inner axes are
+// coalesced and their neighbour re-reads hit in L1/L2.
+#include "kernels.hpp"
+
+namespace tvs {
+namespace {
+
+template <typename T, bool PER>
+__global__ __launch_bounds__(256) void plain1d(const T* __restrict__ in, T* __restrict__ out,
+                                               int64_t n, Coeffs<T> cf) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    if (!PER && (i == 0 || i == n - 1)) {
+        out[i] = in[i];
+        return;
+    }
+    int64_t im = i == 0 ? n - 1 : i - 1;
+    int64_t ip = i == n - 1 ? 0 : i + 1;
+    T acc = cf.c[0] * in[im];
+    acc = acc + cf.c[1] * in[i];
+    acc = acc + cf.c[2] * in[ip];
+    out[i] = acc;
+}
+
+// 2D: thread = one column x, walking `ry` rows with a 3x3 register window.
+template <typename T, bool BOX, bool PER>
+__global__ __launch_bounds__(256) void plain2d(const T* __restrict__ in, T* __restrict__ out,
+                                               int n0, int n1, int ry, Coeffs<T> cf) {
+    using S = Stencil<2, BOX>;
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= n1) return;
+    const int y0 = blockIdx.y * ry;
+    const int y1 = min(y0 + ry, n0);
+    const int xm = PER ? (x == 0 ? n1 - 1 : x - 1) : max(x - 1, 0);
+    const int xp = PER ? (x == n1 - 1 ? 0 : x + 1) : min(x + 1, n1 - 1);
+    const bool col_border = !PER && (x == 0 || x == n1 - 1);
+    auto load_row = [&](int y, T* v) {
+        int yy = PER ? (int)wrap_idx(y, n0) : (int)clamp_idx(y, n0);
+        const T* r = in + (int64_t)yy * n1;
+        v[0] = r[xm];
+        v[1] = r[x];
+        v[2] = r[xp];
+    };
+    T w[3][3];
+    load_row(y0 - 1, w[0]);
+    load_row(y0, w[1]);
+    for (int y = y0; y < y1; ++y) {
+        load_row(y + 1, w[2]);
+        T acc = 0;
+        static_for<0, S::P>([&](auto qc) {
+            constexpr int q = decltype(qc)::value;
+            acc = term(acc, cf.c[q], w[1 + S::off(q, 0)][1 + S::off(q, 1)], q == 0);
+        });
+        if (!PER && (col_border || y == 0 || y == n0 - 1)) acc = w[1][1];
+        out[(int64_t)y * n1 + x] = acc;
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            w[0][i] = w[1][i];
+            w[1][i] = w[2][i];
+        }
+    }
+}
+
+// 3D: thread = one (y, x) column, walking `rz` planes with a 3x3x3 window.
+template <typename T, bool BOX, bool PER>
+__global__ __launch_bounds__(256) void plain3d(const T* __restrict__ in, T* __restrict__ out,
+                                               int n0, int n1, int n2, int rz, Coeffs<T> cf) {
+    using S = Stencil<3, BOX>;
+    const int x = blockIdx.x * 64 + threadIdx.x % 64;
+    const int y = blockIdx.y * 4 + threadIdx.x / 64;
+    if (x >= n2 || y >= n1) return;
+    const int z0 = blockIdx.z * rz;
+    const int z1 = min(z0 + rz, n0);
+    int xs[3], ys[3];
+    for (int d = -1; d <= 1; ++d) {
+        xs[d + 1] = PER ? (int)wrap_idx(x + d, n2) : (int)clamp_idx(x + d, n2);
+        ys[d + 1] = PER ? (int)wrap_idx(y + d, n1) : (int)clamp_idx(y + d, n1);
+    }
+    const bool yx_border = !PER && (x == 0 || x == n2 - 1 || y == 0 || y == n1 - 1);
+    auto load_plane = [&](int z, T (*v)[3]) {
+        int zz = PER ? (int)wrap_idx(z, n0) : (int)clamp_idx(z, n0);
+        const T* p = in + (int64_t)zz * n1 * n2;
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int b = 0; b < 3; ++b) v[a][b] = p[(int64_t)ys[a] * n2 + xs[b]];
+    };
+    T w[3][3][3];
+    load_plane(z0 - 1, w[0]);
+    load_plane(z0, w[1]);
+    for (int z = z0; z < z1; ++z) {
+        load_plane(z + 1, w[2]);
+        T acc = 0;
+        static_for<0, S::P>([&](auto qc) {
+            constexpr int q = decltype(qc)::value;
+            acc = term(acc, cf.c[q],
+                       w[1 + S::off(q, 0)][1 + S::off(q, 1)][1 + S::off(q, 2)], q == 0);
+        });
+        if (!PER && (yx_border || z == 0 || z == n0 - 1)) acc = w[1][1][1];
+        out[((int64_t)z * n1 + y) * n2 + x] = acc;
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int b = 0; b < 3; ++b) {
+                w[0][a][b] = w[1][a][b];
+                w[1][a][b] = w[2][a][b];
+            }
+    }
+}
+
+template <typename T>
+hipError_t plain_step_t(const Problem& p, const T* in, T* out, const Coeffs<T>& cf,
+                        hipStream_t st) {
+    const bool per = p.boundary == TVS_PERIODIC;
+    const bool box = p.shape == TVS_BOX;
+    if (p.ndim == 1) {
+        int64_t n = p.dims[0];
+        dim3 grid((unsigned)((n + 255) / 256));
+        if (per) hipLaunchKernelGGL((plain1d<T, true>), grid, dim3(256), 0, st, in, out, n, cf);
+        else hipLaunchKernelGGL((plain1d<T, false>), grid, dim3(256), 0, st, in, out, n, cf);
+    } else if (p.ndim == 2) {
+        int n0 = (int)p.dims[0], n1 = (int)p.dims[1];
+        const int ry = 16;
+        dim3 grid((unsigned)((n1 + 255) / 256), (unsigned)((n0 + ry - 1) / ry));
+#define TVS_L2(B, PR) \
+    hipLaunchKernelGGL((plain2d<T, B, PR>), grid, dim3(256), 0, st, in, out, n0, n1, ry, cf)
+        if (box) { if (per) TVS_L2(true, true); else TVS_L2(true, false); }
+        else { if (per) TVS_L2(false, true); else TVS_L2(false, false); }
+#undef TVS_L2
+    } else {
+        int n0 = (int)p.dims[0], n1 = (int)p.dims[1], n2 = (int)p.dims[2];
+        const int rz = 16;
+        dim3 grid((unsigned)((n2 + 63) / 64), (unsigned)((n1 + 3) / 4),
+                  (unsigned)((n0 + rz - 1) / rz));
+#define TVS_L3(B, PR) \
+    hipLaunchKernelGGL((plain3d<T, B, PR>), grid, dim3(256), 0, st, in, out, n0, n1, n2, rz, cf)
+        if (box) { if (per) TVS_L3(true, true); else TVS_L3(true, false); }
+        else { if (per) TVS_L3(false, true); else TVS_L3(false, false); }
+#undef TVS_L3
+    }
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_plain_step(const Problem& p, const void* in, void* out, const void* coeffs,
+                             hipStream_t st) {
+    if (p.dtype == TVS_F64)
+        return plain_step_t<double>(p, (const double*)in, (double*)out,
+                                    *(const Coeffs<double>*)coeffs, st);
+    return plain_step_t<float>(p, (const float*)in, (float*)out, *(const Coeffs<float>*)coeffs,
+                               st);
+}
+
+}  // namespace tvs

@@ -1,0 +1,48 @@
+// Kernel launchers shared between the HIP translation units.
+#pragma once
+
+#include "common.hpp"
+
+namespace tvs {
+
+// One plain Jacobi step in -> out (all points written; fixed borders copied).
+hipError_t launch_plain_step(const Problem& p, const void* in, void* out, const void* coeffs,
+                             hipStream_t st);
+
+// Geometry of one time-skewed band: derived from the schedule for a band of
+// `k` levels.  Shared by the launcher, the batch kernel and the tuner.
+struct BandGeom {
+    int k = 1;           // levels in this band
+    int W = 0, H = 1;    // tile extents (halo included) along the last axis / axis 1 (3D)
+    int Wv = 0, Hv = 1;  // valid outputs per tile along those axes
+    int Lv = 0;          // valid outputs per stream segment
+    int C = 1;           // points per lane along the last axis
+    int G = 0;           // lanes per level
+    int NT = 0;          // threads per workgroup
+    int ntx = 1, nty = 1, nseg = 1;  // tile counts
+    int pl = 64;         // 1D: lanes per pipeline
+    int lanemap = 0;
+    size_t lds_bytes = 0;
+    int64_t blocks() const { return (int64_t)ntx * nty * nseg; }
+};
+
+// Fill geometry for a band of k levels; returns false if the schedule cannot
+// run this band (thread or LDS limits).
+bool band_geometry(const Problem& p, const Schedule& s, int k, BandGeom* g);
+
+// One time-skewed band of g.k Jacobi steps in -> out.
+hipError_t launch_tstp_band(const Problem& p, const BandGeom& g, const void* in, void* out,
+                            const void* coeffs, hipStream_t st);
+
+// Gauss-Seidel: `sweeps` in-place sweeps of grid in one persistent launch.
+// `work` is device scratch of gs_work_bytes(p, sweeps) bytes.
+size_t gs_work_bytes(const Problem& p, int sweeps);
+hipError_t launch_gs(const Problem& p, void* grid, const void* coeffs, int sweeps, void* work,
+                     hipStream_t st);
+// Status word written by the Gauss-Seidel kernel (0 = ok) lives in `work`.
+hipError_t gs_read_status(const void* work, int* status, hipStream_t st);
+
+// Whether the schedule's kernel exists for this problem.
+bool tstp_supported(const Problem& p);
+
+}  // namespace tvs

@@ -1,0 +1,239 @@
+// Host-side planning: problem validation, radius and legality, tuning
+// strings and the model-based default schedule.  No device calls here, so a
+// plan can be created (and its validation tested) on a machine without a GPU.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+
+#include "kernels.hpp"
+#include "plan.hpp"
+
+namespace tvs {
+
+static thread_local std::string g_last_error;
+
+int set_error(int code, const std::string& msg) {
+    g_last_error = msg;
+    return code;
+}
+void clear_error() { g_last_error.clear(); }
+const char* last_error() { return g_last_error.c_str(); }
+
+// Radius from the point count (Section 1: "orders (number of neighbors,
+// 3-point, 5-point, ...)"): star P = 2*d*r + 1, box P = (2r+1)^d.
+static int radius_of(int ndim, int shape, int order) {
+    for (int r = 1; r <= 8; ++r) {
+        int P = 1;
+        if (shape == TVS_STAR) {
+            P = 2 * ndim * r + 1;
+        } else {
+            for (int a = 0; a < ndim; ++a) P *= 2 * r + 1;
+        }
+        if (P == order) return r;
+        if (P > order) break;
+    }
+    return -1;
+}
+
+int validate(Problem* pr, int ndim, const int64_t* dims, int dtype, int shape, int order,
+             int dependence, int boundary) {
+    if (!dims) return set_error(TVS_E_INVALID, "dims is NULL");
+    if (ndim < 1 || ndim > 3) return set_error(TVS_E_SHAPE, "ndim must be 1, 2 or 3");
+    if (dtype != TVS_F32 && dtype != TVS_F64) return set_error(TVS_E_INVALID, "bad dtype");
+    if (shape != TVS_STAR && shape != TVS_BOX) return set_error(TVS_E_INVALID, "bad shape");
+    if (dependence != TVS_JACOBI && dependence != TVS_GAUSS_SEIDEL)
+        return set_error(TVS_E_INVALID, "bad dependence");
+    if (boundary != TVS_DIRICHLET && boundary != TVS_PERIODIC)
+        return set_error(TVS_E_INVALID, "bad boundary");
+    const int r = radius_of(ndim, shape, order);
+    if (r < 0)
+        return set_error(TVS_E_ORDER, "order " + std::to_string(order) +
+                                          " is not a star or box point count for ndim " +
+                                          std::to_string(ndim));
+    int64_t total = 1;
+    for (int a = 0; a < ndim; ++a) {
+        if (dims[a] < 2 * r + 1)
+            return set_error(TVS_E_SHAPE, "extent " + std::to_string(dims[a]) + " of axis " +
+                                              std::to_string(a) + " is below 2r+1");
+        if (dims[a] > (int64_t)1 << 30)
+            return set_error(TVS_E_SHAPE, "extent above 2^30");
+        if (total > ((int64_t)1 << 40) / dims[a]) return set_error(TVS_E_SHAPE, "size overflow");
+        total *= dims[a];
+    }
+    if (r != 1) return set_error(TVS_E_UNSUPPORTED, "only radius 1 stencils are implemented");
+    if (dependence == TVS_GAUSS_SEIDEL && boundary == TVS_PERIODIC)
+        return set_error(TVS_E_UNSUPPORTED, "Gauss-Seidel with a periodic boundary");
+    if (dependence == TVS_GAUSS_SEIDEL && ndim != 2)
+        return set_error(TVS_E_UNSUPPORTED, "Gauss-Seidel is implemented for 2D grids");
+    pr->ndim = ndim;
+    for (int a = 0; a < 3; ++a) pr->dims[a] = a < ndim ? dims[a] : 1;
+    pr->dtype = dtype;
+    pr->shape = shape;
+    pr->order = order;
+    pr->dependence = dependence;
+    pr->boundary = boundary;
+    pr->radius = r;
+    return TVS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Tuning strings: "method=tstp,k=8,w=512,l=256,c=8,lanemap=1"
+// ---------------------------------------------------------------------------
+int parse_tuning(const char* str, Schedule* s, bool* has_method) {
+    *has_method = false;
+    if (!str) return TVS_OK;
+    std::string t(str);
+    size_t pos = 0;
+    while (pos < t.size()) {
+        size_t end = t.find(',', pos);
+        if (end == std::string::npos) end = t.size();
+        std::string kv = t.substr(pos, end - pos);
+        pos = end + 1;
+        if (kv.empty()) continue;
+        size_t eq = kv.find('=');
+        if (eq == std::string::npos) return set_error(TVS_E_INVALID, "tuning item without '=': " + kv);
+        std::string key = kv.substr(0, eq), val = kv.substr(eq + 1);
+        if (key == "method") {
+            *has_method = true;
+            if (val == "plain") s->method = TVS_METHOD_PLAIN;
+            else if (val == "tstp") s->method = TVS_METHOD_TSTP;
+            else return set_error(TVS_E_INVALID, "unknown method " + val);
+            continue;
+        }
+        char* e = nullptr;
+        long v = std::strtol(val.c_str(), &e, 10);
+        if (!e || *e || val.empty() || v < 0 || v > (1 << 24))
+            return set_error(TVS_E_INVALID, "bad tuning value " + kv);
+        if (key == "k") s->k = (int)v;
+        else if (key == "s") s->s = (int)v;
+        else if (key == "w") s->w = (int)v;
+        else if (key == "h") s->h = (int)v;
+        else if (key == "l") s->l = (int)v;
+        else if (key == "c") s->c = (int)v;
+        else if (key == "lanemap") s->lanemap = (int)v;
+        else if (key == "pl") s->pl = (int)v;
+        else return set_error(TVS_E_INVALID, "unknown tuning key " + key);
+    }
+    return TVS_OK;
+}
+
+std::string format_tuning(const Problem& p, const Schedule& s) {
+    char buf[160];
+    if (s.method == TVS_METHOD_PLAIN) return "method=plain";
+    if (p.dependence == TVS_GAUSS_SEIDEL) {
+        std::snprintf(buf, sizeof buf, "method=tstp,k=%d", s.k);
+    } else if (p.ndim == 1) {
+        std::snprintf(buf, sizeof buf, "method=tstp,k=%d,l=%d,pl=%d", s.k, s.l, s.pl);
+    } else {
+        std::snprintf(buf, sizeof buf, "method=tstp,k=%d,w=%d,h=%d,l=%d,c=%d,lanemap=%d", s.k,
+                      s.w, s.h, s.l, s.c, s.lanemap);
+    }
+    return buf;
+}
+
+// Workgroups that fit on one CU for a band geometry (LDS and wave limits).
+int wgs_per_cu(const BandGeom& g) {
+    int waves = std::max(1, g.NT / 64);
+    int by_waves = std::max(1, 32 / waves);
+    int by_lds = g.lds_bytes ? (int)((160 * 1024) / g.lds_bytes) : by_waves;
+    return std::max(1, std::min(by_waves, by_lds));
+}
+
+// Modelled time of one band, in units of "one step of one workgroup":
+// rounds of the machine times steps per tile.
+double band_cost(const Problem& p, const BandGeom& g) {
+    const int cus = 256;
+    const double slots = (double)cus * wgs_per_cu(g);
+    const double tiles = (double)g.blocks();
+    const double rounds = std::ceil(tiles / slots);
+    const double steps = g.Lv + 3.0 * g.k;
+    return rounds * steps;
+}
+
+// Choose the stream-segment length for a geometry: the one with the least
+// modelled time over all points, with full-machine rounds.
+void choose_segment(const Problem& p, Schedule* s) {
+    if (p.ndim == 1) return;
+    const int nstream = (int)p.dims[0];
+    double best = 1e300;
+    int best_l = s->l > 0 ? s->l : 256;
+    for (int l = 32; l <= std::max(32, nstream); l += (l < 256 ? 8 : 16)) {
+        Schedule t = *s;
+        t.l = l;
+        BandGeom g;
+        if (!band_geometry(p, t, t.k, &g)) continue;
+        double c = band_cost(p, g);
+        if (c < best - 1e-9) {
+            best = c;
+            best_l = l;
+        }
+        if (l >= nstream) break;
+    }
+    s->l = best_l;
+}
+
+Schedule default_schedule(const Problem& p) {
+    Schedule s;
+    s.method = TVS_METHOD_TSTP;
+    if (p.dependence == TVS_GAUSS_SEIDEL) {
+        s.k = 8;
+        return s;
+    }
+    const bool f64 = p.dtype == TVS_F64;
+    if (p.ndim == 1) {
+        s.pl = 64;
+        s.k = 64;
+        int64_t n = p.dims[0];
+        // enough pipelines to give every SIMD a few, but no shorter than the ramp
+        int64_t l = (n + 2047) / 2048;
+        s.l = (int)std::max<int64_t>(192, std::min<int64_t>(l, 4096));
+        return s;
+    }
+    if (p.ndim == 2) {
+        s.c = 8;
+        s.k = 8;
+        s.w = 512;
+        s.lanemap = 1;
+        // narrow grids: shrink the tile so that it is not mostly halo
+        while (s.w > 64 && s.w - 2 * s.k > 2 * p.dims[1]) s.w /= 2;
+        if (s.w <= 2 * s.k) s.k = std::max(1, s.w / 4);
+    } else {
+        s.c = 8;
+        s.k = 2;
+        s.w = 64;
+        s.h = 32;
+        s.lanemap = 1;
+        (void)f64;
+        while (s.w > 16 && s.w - 2 * s.k > 2 * p.dims[2]) s.w /= 2;
+        while (s.h > 8 && s.h - 2 * s.k > 2 * p.dims[1]) s.h /= 2;
+        while (s.h * s.w / s.c * s.k > 512 && s.c < 16) s.c *= 2;
+    }
+    choose_segment(p, &s);
+    return s;
+}
+
+// Is a schedule runnable for this problem (all bands it will need)?
+int check_schedule(const Problem& p, const Schedule& s) {
+    if (s.method == TVS_METHOD_PLAIN) return TVS_OK;
+    if (s.k < 1) return set_error(TVS_E_INVALID, "k must be >= 1");
+    if (p.dependence == TVS_GAUSS_SEIDEL) {
+        if (s.k > 256) return set_error(TVS_E_INVALID, "k must be <= 256 for Gauss-Seidel");
+        return TVS_OK;
+    }
+    if (s.s != 2)
+        return set_error(TVS_E_INVALID, "skew s = 2 is the only legal choice for radius 1 "
+                                        "(s > max dx/dt) with one barrier per step");
+    for (int kb = 1; kb <= s.k; ++kb) {
+        BandGeom g;
+        if (!band_geometry(p, s, kb, &g))
+            return set_error(TVS_E_INVALID, "schedule cannot run a band of " +
+                                                std::to_string(kb) + " levels: " +
+                                                format_tuning(p, s));
+    }
+    return TVS_OK;
+}
+
+}  // namespace tvs

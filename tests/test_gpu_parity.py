@@ -1,0 +1,122 @@
+"""GPU parity: the HIP library against the CPU oracle, element by element.
+
+FP64 must be bit-identical to the oracle; FP32 must be bit-identical to the
+oracle's FP32 mirror (same operation order in single precision).  Sizes are
+small enough for the oracle, but span several tiles and ragged tails; every
+method (plain one-step launches and the time-skewed pipeline with several
+tile shapes, lane maps and depths) and step counts that leave a remainder
+band are covered, as are the degenerate cases (T = 0, minimal extents,
+tiles larger than the grid, periodic wrap across a whole tile).
+"""
+import numpy as np
+import pytest
+
+from helpers import assert_bitwise, gpu_sweep, oracle_sweep
+from paper_2010_04868_amd.inputs import (BOX, DIRICHLET, F32, F64, GAUSS_SEIDEL, JACOBI,
+                                         PERIODIC, STAR, np_dtype, npoints)
+
+pytestmark = pytest.mark.gpu
+
+SIZES = {
+    1: [(3,), (4,), (97,), (1000,), (4099,)],
+    2: [(3, 3), (5, 7), (37, 53), (70, 130), (131, 67)],
+    3: [(3, 3, 3), (5, 6, 7), (17, 19, 23), (34, 20, 41)],
+}
+TUNINGS = {
+    1: [None, "method=plain", "method=tstp,k=64,l=100,pl=64", "method=tstp,k=16,l=37,pl=16",
+        "method=tstp,k=5,l=20,pl=16", "method=tstp,k=64,l=3,pl=64"],
+    2: [None, "method=plain", "method=tstp,k=4,w=64,c=8,l=40,lanemap=0",
+        "method=tstp,k=4,w=64,c=8,l=40,lanemap=1", "method=tstp,k=3,w=48,c=4,l=17,lanemap=0",
+        "method=tstp,k=8,w=128,c=16,l=64,lanemap=1", "method=tstp,k=16,w=256,c=8,l=50"],
+    3: [None, "method=plain", "method=tstp,k=2,w=16,h=8,c=4,l=10",
+        "method=tstp,k=3,w=16,h=12,c=8,l=7,lanemap=0", "method=tstp,k=1,w=32,h=8,c=16,l=5",
+        "method=tstp,k=2,w=64,h=32,c=8,l=9,lanemap=1"],
+}
+STEPS = [1, 2, 7, 19]
+
+
+def _coeffs(P, seed):
+    # distinct, asymmetric weights: any offset or orientation mix-up shows
+    c = np.random.default_rng(seed).uniform(0.02, 0.2, size=P)
+    return [float(x) for x in c]
+
+
+@pytest.mark.parametrize("ndim,shape", [(1, STAR), (2, STAR), (2, BOX), (3, STAR), (3, BOX)])
+@pytest.mark.parametrize("boundary", [DIRICHLET, PERIODIC])
+@pytest.mark.parametrize("dtype", [F64, F32])
+def test_jacobi_matches_oracle(ndim, shape, boundary, dtype):
+    P = npoints(ndim, shape)
+    coeffs = _coeffs(P, seed=ndim * 10 + shape)
+    failures = []
+    for dims in SIZES[ndim]:
+        u0 = np.random.default_rng(sum(dims)).random(dims).astype(np_dtype(dtype))
+        for T in STEPS + ([130] if ndim == 1 else []):
+            ref = oracle_sweep(u0, coeffs, shape, P, JACOBI, boundary, T)
+            for tuning in TUNINGS[ndim]:
+                got = gpu_sweep(u0, coeffs, shape, P, JACOBI, boundary, T, tuning)
+                try:
+                    assert_bitwise(got, ref, f"dims={dims} T={T} tuning={tuning}")
+                except AssertionError as e:
+                    failures.append(str(e))
+    assert not failures, "\n".join(failures[:20])
+
+
+@pytest.mark.parametrize("shape", [STAR, BOX])
+@pytest.mark.parametrize("dtype", [F64, F32])
+def test_gauss_seidel_matches_oracle(shape, dtype):
+    P = npoints(2, shape)
+    coeffs = _coeffs(P, seed=40 + shape)
+    failures = []
+    for dims in [(3, 3), (5, 7), (66, 70), (67, 130), (131, 40), (200, 129)]:
+        u0 = np.random.default_rng(sum(dims)).random(dims).astype(np_dtype(dtype))
+        for T in (1, 2, 5, 9):
+            ref = oracle_sweep(u0, coeffs, shape, P, GAUSS_SEIDEL, DIRICHLET, T)
+            for tuning in ("method=plain", "method=tstp,k=1", "method=tstp,k=3", None):
+                got = gpu_sweep(u0, coeffs, shape, P, GAUSS_SEIDEL, DIRICHLET, T, tuning)
+                try:
+                    assert_bitwise(got, ref, f"GS dims={dims} T={T} tuning={tuning}")
+                except AssertionError as e:
+                    failures.append(str(e))
+    assert not failures, "\n".join(failures[:20])
+
+
+def test_zero_steps_is_noop():
+    u0 = np.random.default_rng(0).random((40, 50))
+    got = gpu_sweep(u0, [1.0 / 9] * 9, BOX, 9, JACOBI, DIRICHLET, 0)
+    assert_bitwise(got, u0, "T=0")
+
+
+def test_operation_order_and_no_fma_on_gpu():
+    # left-to-right sum: (1 + 1e16) - 1e16 = 0 at the centre point
+    u = np.array([0.0, 1.0, 1e16, -1e16, 0.0])
+    got = gpu_sweep(u, [1.0, 1.0, 1.0], STAR, 3, JACOBI, DIRICHLET, 1, "method=tstp,k=1,l=8,pl=16")
+    assert got[2] == 0.0
+    # no fused multiply-add: -1 + 3*(1/3) is exactly 0 with a rounded product
+    u = np.array([0.0, -1.0, 1.0 / 3.0, 7.0])
+    for tuning in ("method=plain", None):
+        got = gpu_sweep(u, [1.0, 3.0, 0.0], STAR, 3, JACOBI, DIRICHLET, 1, tuning)
+        assert got[2] == 0.0
+    # the same in 2D and 3D kernels: weights put the pattern on one axis
+    u2 = np.zeros((5, 6))
+    u2[1, 2], u2[2, 2], u2[3, 2] = -1.0, 1.0 / 3.0, 7.0  # N, C, S of point (2, 2)
+    c5 = [1.0, 0.0, 3.0, 0.0, 0.0]  # N, W, C, E, S
+    for tuning in ("method=plain", "method=tstp,k=1,w=8,c=4,l=4", None):
+        got = gpu_sweep(u2, c5, STAR, 5, JACOBI, DIRICHLET, 1, tuning)
+        assert got[2, 2] == 0.0, tuning
+    u3 = np.zeros((5, 5, 5))
+    u3[1, 2, 2], u3[2, 2, 2] = -1.0, 1.0 / 3.0
+    c7 = [1.0, 0.0, 0.0, 3.0, 0.0, 0.0, 0.0]
+    for tuning in ("method=plain", "method=tstp,k=1,w=8,h=8,c=4,l=4", None):
+        got = gpu_sweep(u3, c7, STAR, 7, JACOBI, DIRICHLET, 1, tuning)
+        assert got[2, 2, 2] == 0.0, tuning
+
+
+@pytest.mark.parametrize("dep", [JACOBI, GAUSS_SEIDEL])
+def test_composition_bitwise(dep):
+    u0 = np.random.default_rng(7).random((90, 77))
+    c = _coeffs(5, 3)
+    whole = gpu_sweep(u0, c, STAR, 5, dep, DIRICHLET, 23)
+    part = gpu_sweep(gpu_sweep(u0, c, STAR, 5, dep, DIRICHLET, 10), c, STAR, 5, dep, DIRICHLET, 13)
+    assert_bitwise(whole, part, "composition")
+    ref = oracle_sweep(u0, c, STAR, 5, dep, DIRICHLET, 23)
+    assert_bitwise(whole, ref, "vs oracle")
