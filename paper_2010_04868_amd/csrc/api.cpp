@@ -79,8 +79,21 @@ int enqueue_jacobi(tvs_plan* p, void* grid, const CoeffBuf& cb, int64_t T, hipSt
         while (done < T) {
             const int kb = (int)std::min<int64_t>(p->sched.k, T - done);
             BandGeom g = full;
-            if (kb != full.k && !band_geometry(pr, p->sched, kb, &g))
-                return set_error(TVS_E_INVALID, "remainder band does not fit");
+            Schedule rem = p->sched;
+            if (rem.kern == 1) {  // shallower bands: LDS planes on the same tile width
+                rem.kern = 0;
+                rem.w = 64 * rem.c;
+                rem.lanemap = 1;
+            }
+            if (kb != full.k && !band_geometry(pr, rem, kb, &g)) {
+                // a remainder too shallow for the tile shape: plain steps
+                for (int t = 0; t < kb; ++t) {
+                    TVS_HIP_TRY(launch_plain_step(pr, buf[cur], buf[1 - cur], cb.bytes, st));
+                    cur ^= 1;
+                }
+                done += kb;
+                continue;
+            }
             TVS_HIP_TRY(launch_tstp_band(pr, g, buf[cur], buf[1 - cur], cb.bytes, st));
             cur ^= 1;
             done += kb;

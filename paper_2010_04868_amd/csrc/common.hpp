@@ -55,6 +55,7 @@ struct Schedule {
     int c = 1;        // points per lane along the last axis
     int lanemap = 0;  // 0: levels fastest within a wave; 1: columns fastest
     int pl = 64;      // 1D: lanes per pipeline (16 = one DPP row, 64 = a wave)
+    int kern = 0;     // 2D: 0 = levels in lane groups with LDS planes, 1 = levels in registers
 };
 
 // Error reporting: thread-local message + code.
@@ -175,6 +176,16 @@ __device__ __forceinline__ T shift_up(T x, T first) {
     } else {
         return dpp<kDppWaveShr1>(first, x);
     }
+}
+
+// Workgroup barrier that orders LDS only.  __syncthreads() also waits for
+// every outstanding global load and store, which would stall the pipeline on
+// the prefetch it has just issued; the pipeline exchanges data through LDS
+// alone, so an LDS-scoped release/acquire around s_barrier is sufficient.
+__device__ __forceinline__ void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
 // Periodic / clamped index.

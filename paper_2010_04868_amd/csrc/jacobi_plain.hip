@@ -29,89 +29,87 @@ __global__ __launch_bounds__(256) void plain1d(const T* __restrict__ in, T* __re
     out[i] = acc;
 }
 
-// 2D: thread = one column x, walking `ry` rows with a 3x3 register window.
-template <typename T, bool BOX, bool PER>
+// 2D: thread = one column x, `RY` rows; every load of the strip is issued
+// before the first update so that the memory system sees them all at once.
+template <typename T, bool BOX, bool PER, int RY>
 __global__ __launch_bounds__(256) void plain2d(const T* __restrict__ in, T* __restrict__ out,
-                                               int n0, int n1, int ry, Coeffs<T> cf) {
+                                               int n0, int n1, Coeffs<T> cf) {
     using S = Stencil<2, BOX>;
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
     if (x >= n1) return;
-    const int y0 = blockIdx.y * ry;
-    const int y1 = min(y0 + ry, n0);
+    const int y0 = blockIdx.y * RY;
     const int xm = PER ? (x == 0 ? n1 - 1 : x - 1) : max(x - 1, 0);
     const int xp = PER ? (x == n1 - 1 ? 0 : x + 1) : min(x + 1, n1 - 1);
     const bool col_border = !PER && (x == 0 || x == n1 - 1);
-    auto load_row = [&](int y, T* v) {
-        int yy = PER ? (int)wrap_idx(y, n0) : (int)clamp_idx(y, n0);
-        const T* r = in + (int64_t)yy * n1;
-        v[0] = r[xm];
-        v[1] = r[x];
-        v[2] = r[xp];
-    };
-    T w[3][3];
-    load_row(y0 - 1, w[0]);
-    load_row(y0, w[1]);
-    for (int y = y0; y < y1; ++y) {
-        load_row(y + 1, w[2]);
-        T acc = 0;
-        static_for<0, S::P>([&](auto qc) {
-            constexpr int q = decltype(qc)::value;
-            acc = term(acc, cf.c[q], w[1 + S::off(q, 0)][1 + S::off(q, 1)], q == 0);
-        });
-        if (!PER && (col_border || y == 0 || y == n0 - 1)) acc = w[1][1];
-        out[(int64_t)y * n1 + x] = acc;
+    T w[RY + 2][3];
 #pragma unroll
-        for (int i = 0; i < 3; ++i) {
-            w[0][i] = w[1][i];
-            w[1][i] = w[2][i];
+    for (int r = 0; r < RY + 2; ++r) {
+        const int y = y0 - 1 + r;
+        const int yy = PER ? (int)wrap_idx(y, n0) : (int)clamp_idx(y, n0);
+        const T* row = in + (int64_t)yy * n1;
+        w[r][0] = row[xm];
+        w[r][1] = row[x];
+        w[r][2] = row[xp];
+    }
+#pragma unroll
+    for (int r = 0; r < RY; ++r) {
+        const int y = y0 + r;
+        if (y < n0) {
+            T acc = 0;
+            static_for<0, S::P>([&](auto qc) {
+                constexpr int q = decltype(qc)::value;
+                acc = term(acc, cf.c[q], w[r + 1 + S::off(q, 0)][1 + S::off(q, 1)], q == 0);
+            });
+            if (!PER && (col_border || y == 0 || y == n0 - 1)) acc = w[r + 1][1];
+            out[(int64_t)y * n1 + x] = acc;
         }
     }
 }
 
-// 3D: thread = one (y, x) column, walking `rz` planes with a 3x3x3 window.
-template <typename T, bool BOX, bool PER>
+// 3D: thread = one (y, x) column, `RZ` planes, all loads issued first.
+template <typename T, bool BOX, bool PER, int RZ>
 __global__ __launch_bounds__(256) void plain3d(const T* __restrict__ in, T* __restrict__ out,
-                                               int n0, int n1, int n2, int rz, Coeffs<T> cf) {
+                                               int n0, int n1, int n2, Coeffs<T> cf) {
     using S = Stencil<3, BOX>;
     const int x = blockIdx.x * 64 + threadIdx.x % 64;
     const int y = blockIdx.y * 4 + threadIdx.x / 64;
     if (x >= n2 || y >= n1) return;
-    const int z0 = blockIdx.z * rz;
-    const int z1 = min(z0 + rz, n0);
+    const int z0 = blockIdx.z * RZ;
     int xs[3], ys[3];
     for (int d = -1; d <= 1; ++d) {
         xs[d + 1] = PER ? (int)wrap_idx(x + d, n2) : (int)clamp_idx(x + d, n2);
         ys[d + 1] = PER ? (int)wrap_idx(y + d, n1) : (int)clamp_idx(y + d, n1);
     }
     const bool yx_border = !PER && (x == 0 || x == n2 - 1 || y == 0 || y == n1 - 1);
-    auto load_plane = [&](int z, T (*v)[3]) {
-        int zz = PER ? (int)wrap_idx(z, n0) : (int)clamp_idx(z, n0);
-        const T* p = in + (int64_t)zz * n1 * n2;
+    T w[RZ + 2][3][3];
 #pragma unroll
-        for (int a = 0; a < 3; ++a)
-#pragma unroll
-            for (int b = 0; b < 3; ++b) v[a][b] = p[(int64_t)ys[a] * n2 + xs[b]];
-    };
-    T w[3][3][3];
-    load_plane(z0 - 1, w[0]);
-    load_plane(z0, w[1]);
-    for (int z = z0; z < z1; ++z) {
-        load_plane(z + 1, w[2]);
-        T acc = 0;
-        static_for<0, S::P>([&](auto qc) {
-            constexpr int q = decltype(qc)::value;
-            acc = term(acc, cf.c[q],
-                       w[1 + S::off(q, 0)][1 + S::off(q, 1)][1 + S::off(q, 2)], q == 0);
-        });
-        if (!PER && (yx_border || z == 0 || z == n0 - 1)) acc = w[1][1][1];
-        out[((int64_t)z * n1 + y) * n2 + x] = acc;
+    for (int r = 0; r < RZ + 2; ++r) {
+        const int z = z0 - 1 + r;
+        const int zz = PER ? (int)wrap_idx(z, n0) : (int)clamp_idx(z, n0);
+        const T* pl = in + (int64_t)zz * n1 * n2;
 #pragma unroll
         for (int a = 0; a < 3; ++a)
 #pragma unroll
             for (int b = 0; b < 3; ++b) {
-                w[0][a][b] = w[1][a][b];
-                w[1][a][b] = w[2][a][b];
+                // a star stencil reads only the centre column of the outer planes
+                // and the cross of its own plane; the loads it does not need are
+                // dead and removed by the compiler
+                w[r][a][b] = pl[(int64_t)ys[a] * n2 + xs[b]];
             }
+    }
+#pragma unroll
+    for (int r = 0; r < RZ; ++r) {
+        const int z = z0 + r;
+        if (z < n0) {
+            T acc = 0;
+            static_for<0, S::P>([&](auto qc) {
+                constexpr int q = decltype(qc)::value;
+                acc = term(acc, cf.c[q],
+                           w[r + 1 + S::off(q, 0)][1 + S::off(q, 1)][1 + S::off(q, 2)], q == 0);
+            });
+            if (!PER && (yx_border || z == 0 || z == n0 - 1)) acc = w[r + 1][1][1];
+            out[((int64_t)z * n1 + y) * n2 + x] = acc;
+        }
     }
 }
 
@@ -127,20 +125,20 @@ hipError_t plain_step_t(const Problem& p, const T* in, T* out, const Coeffs<T>& 
         else hipLaunchKernelGGL((plain1d<T, false>), grid, dim3(256), 0, st, in, out, n, cf);
     } else if (p.ndim == 2) {
         int n0 = (int)p.dims[0], n1 = (int)p.dims[1];
-        const int ry = 16;
+        constexpr int ry = 8;
         dim3 grid((unsigned)((n1 + 255) / 256), (unsigned)((n0 + ry - 1) / ry));
 #define TVS_L2(B, PR) \
-    hipLaunchKernelGGL((plain2d<T, B, PR>), grid, dim3(256), 0, st, in, out, n0, n1, ry, cf)
+    hipLaunchKernelGGL((plain2d<T, B, PR, ry>), grid, dim3(256), 0, st, in, out, n0, n1, cf)
         if (box) { if (per) TVS_L2(true, true); else TVS_L2(true, false); }
         else { if (per) TVS_L2(false, true); else TVS_L2(false, false); }
 #undef TVS_L2
     } else {
         int n0 = (int)p.dims[0], n1 = (int)p.dims[1], n2 = (int)p.dims[2];
-        const int rz = 16;
+        constexpr int rz = 4;
         dim3 grid((unsigned)((n2 + 63) / 64), (unsigned)((n1 + 3) / 4),
                   (unsigned)((n0 + rz - 1) / rz));
 #define TVS_L3(B, PR) \
-    hipLaunchKernelGGL((plain3d<T, B, PR>), grid, dim3(256), 0, st, in, out, n0, n1, n2, rz, cf)
+    hipLaunchKernelGGL((plain3d<T, B, PR, rz>), grid, dim3(256), 0, st, in, out, n0, n1, n2, cf)
         if (box) { if (per) TVS_L3(true, true); else TVS_L3(true, false); }
         else { if (per) TVS_L3(false, true); else TVS_L3(false, false); }
 #undef TVS_L3

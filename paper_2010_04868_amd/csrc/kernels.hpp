@@ -22,8 +22,11 @@ struct BandGeom {
     int ntx = 1, nty = 1, nseg = 1;  // tile counts
     int pl = 64;         // 1D: lanes per pipeline
     int lanemap = 0;
+    int kern = 0;        // 0 = LDS level planes, 1 = register pipeline (2D)
     size_t lds_bytes = 0;
-    int64_t blocks() const { return (int64_t)ntx * nty * nseg; }
+    int tiles_per_block = 1;  // register pipeline: one tile per wave, four waves
+    int64_t tiles() const { return (int64_t)ntx * nty * nseg; }
+    int64_t blocks() const { return (tiles() + tiles_per_block - 1) / tiles_per_block; }
 };
 
 // Fill geometry for a band of k levels; returns false if the schedule cannot

@@ -115,6 +115,7 @@ int parse_tuning(const char* str, Schedule* s, bool* has_method) {
         else if (key == "c") s->c = (int)v;
         else if (key == "lanemap") s->lanemap = (int)v;
         else if (key == "pl") s->pl = (int)v;
+        else if (key == "kern") s->kern = (int)v;
         else return set_error(TVS_E_INVALID, "unknown tuning key " + key);
     }
     return TVS_OK;
@@ -128,16 +129,18 @@ std::string format_tuning(const Problem& p, const Schedule& s) {
     } else if (p.ndim == 1) {
         std::snprintf(buf, sizeof buf, "method=tstp,k=%d,l=%d,pl=%d", s.k, s.l, s.pl);
     } else {
-        std::snprintf(buf, sizeof buf, "method=tstp,k=%d,w=%d,h=%d,l=%d,c=%d,lanemap=%d", s.k,
-                      s.w, s.h, s.l, s.c, s.lanemap);
+        std::snprintf(buf, sizeof buf, "method=tstp,k=%d,w=%d,h=%d,l=%d,c=%d,lanemap=%d,kern=%d",
+                      s.k, s.w, s.h, s.l, s.c, s.lanemap, s.kern);
     }
     return buf;
 }
 
 // Workgroups that fit on one CU for a band geometry (LDS and wave limits).
 int wgs_per_cu(const BandGeom& g) {
-    int waves = std::max(1, g.NT / 64);
-    int by_waves = std::max(1, 32 / waves);
+    // the LDS pipelines use about 100-128 VGPRs (four waves per SIMD), the
+    // register pipeline about 250 (two waves per SIMD)
+    int waves = std::max(1, (g.NT + 63) / 64);
+    int by_waves = std::max(1, (g.kern == 1 ? 8 : 16) / waves);
     int by_lds = g.lds_bytes ? (int)((160 * 1024) / g.lds_bytes) : by_waves;
     return std::max(1, std::min(by_waves, by_lds));
 }
@@ -149,7 +152,7 @@ double band_cost(const Problem& p, const BandGeom& g) {
     const double slots = (double)cus * wgs_per_cu(g);
     const double tiles = (double)g.blocks();
     const double rounds = std::ceil(tiles / slots);
-    const double steps = g.Lv + 3.0 * g.k;
+    const double steps = g.Lv + (g.kern == 1 ? 2.0 : 3.0) * g.k;
     return rounds * steps;
 }
 
@@ -193,10 +196,12 @@ Schedule default_schedule(const Problem& p) {
         return s;
     }
     if (p.ndim == 2) {
-        s.c = 8;
+        // measured best on the 8192^2 FP64 box stencil: 4 points per lane,
+        // 8 levels, successive levels in successive lanes
+        s.c = 4;
         s.k = 8;
-        s.w = 512;
-        s.lanemap = 1;
+        s.w = 256;
+        s.lanemap = 0;
         // narrow grids: shrink the tile so that it is not mostly halo
         while (s.w > 64 && s.w - 2 * s.k > 2 * p.dims[1]) s.w /= 2;
         if (s.w <= 2 * s.k) s.k = std::max(1, s.w / 4);
@@ -226,13 +231,12 @@ int check_schedule(const Problem& p, const Schedule& s) {
     if (s.s != 2)
         return set_error(TVS_E_INVALID, "skew s = 2 is the only legal choice for radius 1 "
                                         "(s > max dx/dt) with one barrier per step");
-    for (int kb = 1; kb <= s.k; ++kb) {
-        BandGeom g;
-        if (!band_geometry(p, s, kb, &g))
-            return set_error(TVS_E_INVALID, "schedule cannot run a band of " +
-                                                std::to_string(kb) + " levels: " +
-                                                format_tuning(p, s));
-    }
+    // the full band must fit; shallower remainder bands that do not fit the
+    // tile shape run as plain steps
+    BandGeom g;
+    if (!band_geometry(p, s, s.k, &g))
+        return set_error(TVS_E_INVALID, "schedule cannot run a band of " + std::to_string(s.k) +
+                                            " levels: " + format_tuning(p, s));
     return TVS_OK;
 }
 

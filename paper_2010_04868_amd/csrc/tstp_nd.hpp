@@ -1,0 +1,372 @@
+// Time-skewed temporal pipeline for 2D and 3D Jacobi stencils.
+//
+// Temporal vectorization applies to the outermost space loop only (Section
+// 3.2, "High-dimensional Stencils"), so axis 0 is the stream axis and the
+// other axes are tiled.  A workgroup owns one tile and a segment of the
+// stream axis for a band of k time steps.  Its lanes are grouped by time
+// level: lane group j (j = 1..k) holds level t0+j.  At every step all levels
+// advance one stream position together, level j working s = 2 positions
+// behind level j-1, so a vector of lanes holds points of k successive time
+// levels at skewed stream positions -- the paper's input/output vectors --
+// and no lane ever waits for a value of its own step (the legality
+// condition s > max dx/dt of Section 3.2 is s >= 2 for radius 1).
+//
+// The values a level hands to the next are stored in LDS, one plane per
+// level and stream position parity (Section 3.2: in higher dimensions the
+// reorganized input vectors are stored for the following outer iterations).
+// Within a plane row, element x of lane group g = x / C sits at
+// (x mod C) * S + g + 1: same-position values of consecutive lanes are
+// contiguous -- the transposed layout of Section 3.3 -- which makes every
+// read and write of the pipeline free of bank conflicts.  One barrier per
+// step separates the writers of one parity from the readers of the other.
+//
+// Level 0 is staged from HBM a few steps ahead; level k goes through its own
+// LDS plane and is stored by all threads one step later, so loads and stores
+// are coalesced and each grid value crosses HBM once per band of k steps.  Tiles overlap by k
+// points per side on the tiled axes and at the segment ends (a trapezoid in
+// time), so workgroups never wait for each other.
+//
+// Every level computes each point with the canonical operation order,
+// carried as three running sums per point: the terms of the stencil row
+// behind the point along the stream axis, at it, and ahead of it -- contiguous
+// runs of the canonical order.  When all weights are equal the product of a
+// value and the weight is computed once per value and used by every term
+// that needs it; a product is the same rounded number wherever it is used,
+// so this changes no bit.  The result is bit-identical to the naive sweep.
+#pragma once
+
+#include "kernels.hpp"
+
+namespace tvs {
+namespace nd {
+
+struct ArgsNd {
+    int nz, ny, nx;   // stream axis, axis 1 (3D only, else 1), last axis
+    int k;
+    int W, H;         // tile extents (halo included)
+    int Wv, Hv;       // valid extents
+    int S;            // LDS sub-row stride (elements); row stride is C*S
+    int Wp;           // LDS row stride (elements)
+    int PSP;          // LDS plane stride (elements)
+    int G, Gx, NT;    // lanes per level, lane groups per tile row, threads
+    int Lv, Lin;
+    int ntx, nty;
+    int lanemap;
+};
+
+template <typename T, int D, bool BOX, bool PER, int C, int NPT, bool UNI>
+__global__ __launch_bounds__(512) void tstp_nd(const T* __restrict__ in, T* __restrict__ out,
+                                               ArgsNd a, Coeffs<T> cf) {
+    using St = Stencil<D, BOX>;
+    constexpr int gm_b = St::group_begin(-1), gm_e = St::group_end(-1);
+    constexpr int g0_b = St::group_begin(0), g0_e = St::group_end(0);
+    constexpr int gp_b = St::group_begin(1), gp_e = St::group_end(1);
+    static_assert(gm_b == 0 && gm_e == g0_b && g0_e == gp_b && gp_e == St::P, "canonical groups");
+    constexpr int R = D == 3 ? 3 : 1;  // plane rows a lane reads
+    constexpr int MID = D == 3 ? 1 : 0;
+
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
+    T* lds = reinterpret_cast<T*>(smem_raw);
+
+    const int tid = threadIdx.x;
+    const int k = a.k;
+    const int S = a.S;
+    const int Wp = a.Wp;
+    int b = blockIdx.x;
+    const int bx = b % a.ntx;
+    b /= a.ntx;
+    const int by = b % a.nty;
+    const int bs = b / a.nty;
+    const int x_org = bx * a.Wv - k;
+    const int y_org = D == 3 ? by * a.Hv - k : 0;
+    const int z_org = bs * a.Lv - k;
+
+    int j, g;
+    if (a.lanemap == 0) {
+        j = 1 + tid % k;
+        g = tid / k;
+    } else {
+        j = 1 + tid / a.G;
+        g = tid % a.G;
+    }
+    const int ly = D == 3 ? g / a.Gx : 0;  // lane's tile row (3D)
+    const int gx = g - ly * a.Gx;          // lane group within the row
+    const int lx = gx * C;                 // lane's first tile column
+
+    // Dirichlet: does this tile touch a fixed border?  (uniform branch)
+    bool border_tile = false;
+    if (!PER) {
+        border_tile = x_org <= 0 || x_org + a.W - 1 >= a.nx - 1 || z_org <= 0 ||
+                      z_org + a.Lin - 1 >= a.nz - 1;
+        if (D == 3) border_tile = border_tile || y_org <= 0 || y_org + a.H - 1 >= a.ny - 1;
+    }
+    const int gy_lane = y_org + ly;
+    const bool y_border = D == 3 && !PER && (gy_lane == 0 || gy_lane == a.ny - 1);
+
+    // zero the LDS planes once (pads stay zero; they only feed invalid points)
+    for (int e = tid; e < (k + 1) * 2 * a.PSP; e += a.NT) lds[e] = T(0);
+
+    // Staging: thread handles elements e = tid + i*NT of a tile plane, both to
+    // load level 0 from HBM into LDS and to store level k from LDS to HBM.
+    // The LDS position of element (row yl, column xl) is the one the lanes use.
+    const int PS = a.H * a.W;
+    int st_lds[NPT], st_g[NPT], st_out[NPT];
+#pragma unroll
+    for (int i = 0; i < NPT; ++i) {
+        const int e = tid + i * a.NT;
+        st_lds[i] = -1;
+        st_g[i] = 0;
+        st_out[i] = -1;
+        if (e < PS) {
+            const int yl = D == 3 ? e / a.W : 0;
+            const int xl = e - yl * a.W;
+            const int ox = x_org + xl, oy = y_org + yl;
+            int gxx = PER ? (int)wrap_idx(ox, a.nx) : (int)clamp_idx(ox, a.nx);
+            int gyy = D == 3 ? (PER ? (int)wrap_idx(oy, a.ny) : (int)clamp_idx(oy, a.ny)) : 0;
+            st_lds[i] = (D == 3 ? (yl + 1) * Wp : 0) + (xl % C) * S + xl / C + 1;
+            st_g[i] = gyy * a.nx + gxx;
+            const bool valid = xl >= k && xl < a.W - k && ox < a.nx &&
+                               (D != 3 || (yl >= k && yl < a.H - k && oy < a.ny));
+            if (valid) st_out[i] = oy * a.nx + ox;
+        }
+    }
+    const int64_t plane_elems = (int64_t)a.ny * a.nx;
+    auto issue_load = [&](int q, T* dst) {
+        if (q >= a.Lin) return;
+        int64_t gz = z_org + q;
+        gz = PER ? wrap_idx(gz, a.nz) : clamp_idx(gz, a.nz);
+        const T* src = in + gz * plane_elems;
+#pragma unroll
+        for (int i = 0; i < NPT; ++i)
+            if (st_lds[i] >= 0) dst[i] = src[st_g[i]];
+    };
+    auto store_input = [&](int q, const T* v) {
+        if (q >= a.Lin) return;
+        T* pl = lds + (q & 1) * a.PSP;  // level 0, parity q&1
+#pragma unroll
+        for (int i = 0; i < NPT; ++i)
+            if (st_lds[i] >= 0) pl[st_lds[i]] = v[i];
+    };
+    // level k emitted tile row q-1-2k at step q-1 into its plane; write it out
+    auto store_output = [&](int q) {
+        const int row = q - 1 - 2 * k;
+        if (row < k || row >= a.Lin - k) return;
+        const int64_t gz = (int64_t)z_org + row;
+        if (gz >= a.nz) return;
+        const T* pl = lds + (k * 2 + ((q - 1) & 1)) * a.PSP;
+        T* o = out + gz * plane_elems;
+#pragma unroll
+        for (int i = 0; i < NPT; ++i)
+            if (st_out[i] >= 0) o[st_out[i]] = pl[st_lds[i]];
+    };
+
+    T Sacc[C], Macc[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) Sacc[c] = Macc[c] = T(0);
+    const T cu = cf.c[0];  // the common weight when UNI
+
+    const int row_off = D == 3 ? ly * Wp : 0;  // padded row ly holds tile row ly-1
+    // level-0 planes are loaded DP steps before they enter LDS: the wait for a
+    // load then also covers the stores issued before it, which are DP steps old
+    constexpr int DP = 4;
+    T pre[DP][NPT];
+#pragma unroll
+    for (int d = 0; d < DP; ++d)
+#pragma unroll
+        for (int i = 0; i < NPT; ++i) pre[d][i] = T(0);
+
+    auto step = [&](int q, T* pr) {
+        store_input(q, pr);
+        issue_load(q + DP, pr);
+        store_output(q);
+        const int p = q - 2 * j + 1;  // stream position of the level-(j-1) plane read now
+        if (p >= 0 && p < a.Lin) {
+            const T* src = lds + ((j - 1) * 2 + ((q - 1) & 1)) * a.PSP + row_off;
+            // v[r][i]: plane row ly-1+r, tile column lx-1+i (multiplied by the
+            // common weight when UNI)
+            T v[R][C + 2];
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const T* rs = src + r * Wp;
+#pragma unroll
+                for (int i = 0; i < C + 2; ++i) {
+                    const bool need = BOX || r == MID || (i >= 1 && i <= C);
+                    if (!need) continue;
+                    const int pos = i == 0 ? (C - 1) * S + gx : i <= C ? (i - 1) * S + gx + 1 : gx + 2;
+                    v[r][i] = rs[pos];
+                }
+            }
+            if (UNI) {
+#pragma unroll
+                for (int r = 0; r < R; ++r)
+#pragma unroll
+                    for (int i = 0; i < C + 2; ++i) {
+                        const bool need = BOX || r == MID || (i >= 1 && i <= C);
+                        if (need) v[r][i] = cu * v[r][i];
+                    }
+            }
+            auto val = [&](auto qc, int c) -> T {
+                constexpr int q2 = decltype(qc)::value;
+                if constexpr (D == 3)
+                    return v[1 + St::off(q2, 1)][1 + c + St::off(q2, 2)];
+                else
+                    return v[0][1 + c + St::off(q2, 1)];
+            };
+            // one canonical term: weight * value, or the shared product
+            auto add = [&](T acc, auto qc, int c, bool first) -> T {
+                constexpr int q2 = decltype(qc)::value;
+                const T prod = UNI ? val(qc, c) : cf.c[q2] * val(qc, c);
+                return first ? prod : acc + prod;
+            };
+            const int gz_out = z_org + p - 1;
+            const bool z_border = !PER && (gz_out == 0 || gz_out == a.nz - 1);
+            const bool emit = p >= 1;
+            T* dst = lds + (j * 2 + (q & 1)) * a.PSP + (D == 3 ? row_off + Wp : 0) + gx + 1;
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                T f = Macc[c];
+                static_for<gp_b, gp_e>([&](auto qc) { f = add(f, qc, c, false); });
+                T m = Sacc[c];
+                static_for<g0_b, g0_e>([&](auto qc) { m = add(m, qc, c, false); });
+                T s = T(0);
+                static_for<gm_b, gm_e>([&](auto qc) {
+                    s = add(s, qc, c, decltype(qc)::value == gm_b);
+                });
+                if (!PER && border_tile) {
+                    // a fixed border point keeps its input value at every level
+                    const int gxc = x_org + lx + c;
+                    if ((z_border || y_border || gxc == 0 || gxc == a.nx - 1) && gz_out >= 0 &&
+                        gz_out < a.nz && gxc >= 0 && gxc < a.nx &&
+                        (D != 3 || (gy_lane >= 0 && gy_lane < a.ny)))
+                        f = in[((int64_t)gz_out * a.ny + (D == 3 ? gy_lane : 0)) * a.nx + gxc];
+                }
+                Macc[c] = m;
+                Sacc[c] = s;
+                if (emit) dst[c * S] = f;
+            }
+        }
+        lds_barrier();
+    };
+
+    lds_barrier();  // LDS zeroed
+#pragma unroll
+    for (int d = 0; d < DP; ++d) issue_load(d, pre[d]);
+    // level k emits its last row at step Lin+k-1; it is stored one step later
+    const int Q = a.Lin + k + 1;
+    for (int q = 0; q < Q; q += DP) {
+        static_for<0, DP>([&](auto dc) {
+            constexpr int d = decltype(dc)::value;
+            if (q + d < Q) step(q + d, pre[d]);
+        });
+    }
+}
+
+// LDS sub-row stride: at least Gx+2, and congruent to 16/C modulo 32/C, so
+// that the 16 lanes of one LDS cycle hit distinct banks both when lanes read
+// their neighbours (consecutive lane groups) and when staging threads write a
+// row in order (consecutive columns, i.e. C sub-rows x 16/C lane groups).
+inline int lds_sub_stride(int Gx, int C) {
+    const int want = 16 / C, mod = 32 / C;
+    int S = Gx + 2;
+    while (S % mod != want % mod) ++S;
+    return S;
+}
+
+// Plane stride: padded so that lanes of different levels in one 16-lane
+// group (lane map 0) fall on different banks.
+inline int lds_plane_stride(int elems, int k, int lanemap) {
+    int kk = k >= 16 ? 16 : k >= 8 ? 8 : k >= 4 ? 4 : k >= 2 ? 2 : 1;
+    const int want = lanemap == 0 ? 16 / kk : 1;
+    int P = elems;
+    while (P % 16 != want % 16) ++P;
+    return P;
+}
+
+template <typename T, int D>
+hipError_t launch_nd_impl(const Problem& p, const BandGeom& g, const T* in, T* out,
+                          const Coeffs<T>& cf, bool uniform, hipStream_t st) {
+    ArgsNd a{};
+    a.nz = (int)p.dims[0];
+    a.ny = D == 3 ? (int)p.dims[1] : 1;
+    a.nx = (int)p.dims[D - 1];
+    a.k = g.k;
+    a.W = g.W;
+    a.H = g.H;
+    a.Wv = g.Wv;
+    a.Hv = g.Hv;
+    a.Gx = g.W / g.C;
+    a.S = lds_sub_stride(a.Gx, g.C);
+    a.Wp = g.C * a.S;
+    a.PSP = lds_plane_stride(D == 3 ? (g.H + 2) * a.Wp : a.Wp, g.k, g.lanemap);
+    a.G = g.G;
+    a.NT = g.NT;
+    a.Lv = g.Lv;
+    a.Lin = g.Lv + 2 * g.k;
+    a.ntx = g.ntx;
+    a.nty = g.nty;
+    a.lanemap = g.lanemap;
+    const size_t lds = (size_t)(g.k + 1) * 2 * a.PSP * sizeof(T);
+    const int npt = (a.H * a.W + a.NT - 1) / a.NT;  // plane elements per thread
+    const bool box = p.shape == TVS_BOX, per = p.boundary == TVS_PERIODIC;
+    dim3 grid((unsigned)g.blocks()), block((unsigned)g.NT);
+    hipError_t err = hipErrorInvalidValue;
+    auto go = [&](auto kern) {
+        static bool attr_set = false;  // per instantiation
+        if (!attr_set) {
+            (void)hipFuncSetAttribute((const void*)kern,
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+            attr_set = true;
+        }
+        hipLaunchKernelGGL(kern, grid, block, lds, st, in, out, a, cf);
+        err = hipGetLastError();
+    };
+#define TVS_ND(B, PR, CC, N, U) go(tstp_nd<T, D, B, PR, CC, N, U>)
+#define TVS_ND_U(B, PR, CC, N) \
+    do { if (uniform) TVS_ND(B, PR, CC, N, true); else TVS_ND(B, PR, CC, N, false); } while (0)
+#define TVS_ND_N(B, PR, CC)                               \
+    do {                                                  \
+        if (npt <= 1) TVS_ND_U(B, PR, CC, 1);             \
+        else if (npt <= 2) TVS_ND_U(B, PR, CC, 2);        \
+        else if (npt <= 4) TVS_ND_U(B, PR, CC, 4);        \
+        else return hipErrorInvalidValue;                 \
+    } while (0)
+#define TVS_ND_C(B, PR)                      \
+    switch (g.C) {                           \
+        case 4: TVS_ND_N(B, PR, 4); break;   \
+        case 8: TVS_ND_N(B, PR, 8); break;   \
+        case 16: TVS_ND_N(B, PR, 16); break; \
+        default: return hipErrorInvalidValue; \
+    }
+    if (box) {
+        if (per) { TVS_ND_C(true, true) } else { TVS_ND_C(true, false) }
+    } else {
+        if (per) { TVS_ND_C(false, true) } else { TVS_ND_C(false, false) }
+    }
+#undef TVS_ND_C
+#undef TVS_ND_N
+#undef TVS_ND_U
+#undef TVS_ND
+    return err;
+}
+
+}  // namespace nd
+
+// LDS bytes a band of this geometry needs (same formula as the launcher).
+inline size_t tstp_nd_lds_bytes(const Problem& p, const BandGeom& g) {
+    const int Gx = g.W / g.C;
+    const int S = nd::lds_sub_stride(Gx, g.C);
+    const int Wp = g.C * S;
+    const int PSP = nd::lds_plane_stride(p.ndim == 3 ? (g.H + 2) * Wp : Wp, g.k, g.lanemap);
+    return (size_t)(g.k + 1) * 2 * PSP * p.elem_bytes();
+}
+
+hipError_t launch_nd_f64_2d(const Problem&, const BandGeom&, const double*, double*,
+                            const Coeffs<double>&, bool, hipStream_t);
+hipError_t launch_nd_f64_3d(const Problem&, const BandGeom&, const double*, double*,
+                            const Coeffs<double>&, bool, hipStream_t);
+hipError_t launch_nd_f32_2d(const Problem&, const BandGeom&, const float*, float*,
+                            const Coeffs<float>&, bool, hipStream_t);
+hipError_t launch_nd_f32_3d(const Problem&, const BandGeom&, const float*, float*,
+                            const Coeffs<float>&, bool, hipStream_t);
+
+}  // namespace tvs
