@@ -5,22 +5,10 @@
 namespace tvs {
 bool tune_cache_lookup(const Problem&, Schedule*) { return false; }
 void tune_cache_store(const Problem&, const Schedule&) {}
-void graph_cache_drop(tvs_plan*) {}
 }  // namespace tvs
 
 using namespace tvs;
 extern "C" {
-int stencil_batch_run(int n, tvs_plan* const* plans, void* const* grids,
-                      const double* const* coeffs, const int64_t* T, void* stream) {
-    clear_error();
-    if (n < 0 || (n > 0 && (!plans || !grids || !coeffs || !T)))
-        return set_error(TVS_E_INVALID, "NULL argument");
-    for (int i = 0; i < n; ++i) {
-        int rc = stencil_run(plans[i], grids[i], coeffs[i], T[i], stream);
-        if (rc) return rc;
-    }
-    return TVS_OK;
-}
 int stencil_tune(tvs_plan*, void*, const double*, int64_t, void*, char*, size_t) {
     return set_error(TVS_E_UNSUPPORTED, "not built yet");
 }

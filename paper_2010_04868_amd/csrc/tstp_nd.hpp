@@ -54,9 +54,12 @@ struct ArgsNd {
     int lanemap;
 };
 
+// One tile of one band.  Threads tid >= a.NT take part in the barriers only.
+// Returns after a final LDS barrier, so the caller may reuse the LDS.
 template <typename T, int D, bool BOX, bool PER, int C, int NPT, bool UNI>
-__global__ __launch_bounds__(512) void tstp_nd(const T* __restrict__ in, T* __restrict__ out,
-                                               ArgsNd a, Coeffs<T> cf) {
+__device__ __forceinline__ void tstp_tile(const T* __restrict__ in, T* __restrict__ out,
+                                          const ArgsNd& a, const Coeffs<T>& cf, int tile, T* lds,
+                                          int tid) {
     using St = Stencil<D, BOX>;
     constexpr int gm_b = St::group_begin(-1), gm_e = St::group_end(-1);
     constexpr int g0_b = St::group_begin(0), g0_e = St::group_end(0);
@@ -65,14 +68,11 @@ __global__ __launch_bounds__(512) void tstp_nd(const T* __restrict__ in, T* __re
     constexpr int R = D == 3 ? 3 : 1;  // plane rows a lane reads
     constexpr int MID = D == 3 ? 1 : 0;
 
-    extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
-    T* lds = reinterpret_cast<T*>(smem_raw);
-
-    const int tid = threadIdx.x;
+    const bool worker = tid < a.NT;
     const int k = a.k;
     const int S = a.S;
     const int Wp = a.Wp;
-    int b = blockIdx.x;
+    int b = tile;
     const int bx = b % a.ntx;
     b /= a.ntx;
     const int by = b % a.nty;
@@ -89,6 +89,10 @@ __global__ __launch_bounds__(512) void tstp_nd(const T* __restrict__ in, T* __re
         j = 1 + tid / a.G;
         g = tid % a.G;
     }
+    if (!worker) {  // idle thread: keep it out of every level's range
+        j = 1 << 20;
+        g = 0;
+    }
     const int ly = D == 3 ? g / a.Gx : 0;  // lane's tile row (3D)
     const int gx = g - ly * a.Gx;          // lane group within the row
     const int lx = gx * C;                 // lane's first tile column
@@ -104,7 +108,8 @@ __global__ __launch_bounds__(512) void tstp_nd(const T* __restrict__ in, T* __re
     const bool y_border = D == 3 && !PER && (gy_lane == 0 || gy_lane == a.ny - 1);
 
     // zero the LDS planes once (pads stay zero; they only feed invalid points)
-    for (int e = tid; e < (k + 1) * 2 * a.PSP; e += a.NT) lds[e] = T(0);
+    if (worker)
+        for (int e = tid; e < (k + 1) * 2 * a.PSP; e += a.NT) lds[e] = T(0);
 
     // Staging: thread handles elements e = tid + i*NT of a tile plane, both to
     // load level 0 from HBM into LDS and to store level k from LDS to HBM.
@@ -117,7 +122,7 @@ __global__ __launch_bounds__(512) void tstp_nd(const T* __restrict__ in, T* __re
         st_lds[i] = -1;
         st_g[i] = 0;
         st_out[i] = -1;
-        if (e < PS) {
+        if (worker && e < PS) {
             const int yl = D == 3 ? e / a.W : 0;
             const int xl = e - yl * a.W;
             const int ox = x_org + xl, oy = y_org + yl;
@@ -261,6 +266,14 @@ __global__ __launch_bounds__(512) void tstp_nd(const T* __restrict__ in, T* __re
     }
 }
 
+template <typename T, int D, bool BOX, bool PER, int C, int NPT, bool UNI>
+__global__ __launch_bounds__(512) void tstp_nd(const T* __restrict__ in, T* __restrict__ out,
+                                               ArgsNd a, Coeffs<T> cf) {
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
+    tstp_tile<T, D, BOX, PER, C, NPT, UNI>(in, out, a, cf, blockIdx.x,
+                                           reinterpret_cast<T*>(smem_raw), threadIdx.x);
+}
+
 // LDS sub-row stride: at least Gx+2, and congruent to 16/C modulo 32/C, so
 // that the 16 lanes of one LDS cycle hit distinct banks both when lanes read
 // their neighbours (consecutive lane groups) and when staging threads write a
@@ -282,9 +295,9 @@ inline int lds_plane_stride(int elems, int k, int lanemap) {
     return P;
 }
 
-template <typename T, int D>
-hipError_t launch_nd_impl(const Problem& p, const BandGeom& g, const T* in, T* out,
-                          const Coeffs<T>& cf, bool uniform, hipStream_t st) {
+// Kernel arguments of a band (host side).
+inline ArgsNd make_args(const Problem& p, const BandGeom& g) {
+    const int D = p.ndim;
     ArgsNd a{};
     a.nz = (int)p.dims[0];
     a.ny = D == 3 ? (int)p.dims[1] : 1;
@@ -305,6 +318,13 @@ hipError_t launch_nd_impl(const Problem& p, const BandGeom& g, const T* in, T* o
     a.ntx = g.ntx;
     a.nty = g.nty;
     a.lanemap = g.lanemap;
+    return a;
+}
+
+template <typename T, int D>
+hipError_t launch_nd_impl(const Problem& p, const BandGeom& g, const T* in, T* out,
+                          const Coeffs<T>& cf, bool uniform, hipStream_t st) {
+    const ArgsNd a = make_args(p, g);
     const size_t lds = (size_t)(g.k + 1) * 2 * a.PSP * sizeof(T);
     const int npt = (a.H * a.W + a.NT - 1) / a.NT;  // plane elements per thread
     const bool box = p.shape == TVS_BOX, per = p.boundary == TVS_PERIODIC;
