@@ -3,16 +3,24 @@
 
 One "step" of this benchmark is one full solve of the headline workload --
 2D 9-point box Jacobi on an 8192 x 8192 FP64 grid (zero border, all weights
-1/9), T = 1000 time steps -- on a grid already resident in HBM.  The JSON
-line also carries the plain one-step-per-launch sweep on the same grid, the
-roofline position of the dominant kernel, and the CPU oracle timed on a
-bounded sample of the same workload.
+1/9), T = 1000 time steps -- on a grid already resident in HBM, with the
+schedule the autotuner picks.  The JSON line also carries:
+  * the plain one-step-per-launch sweep on the same grid (the baseline the
+    time-skewed forms must beat);
+  * the roofline position of the dominant kernel (one band of k steps),
+    timed live with HIP events;
+  * a serving run: a Poisson stream of mixed 1D/2D/3D Jacobi and 2D
+    Gauss-Seidel solves through the continuous-batching server, p50/p99
+    latency and throughput, next to the same requests run one at a time;
+  * the CPU oracle timed on a bounded sample of the headline workload.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -22,13 +30,38 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 # FP64 vector: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.3e12 separately
 # issued multiplies or adds per second (the 78.6 TFLOP/s figure counts an FMA
-# as two; the bit-exact update uses no FMA).  FP32 non-packed: the same.
+# as two; the bit-exact update uses no FMA).
 ALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 METRIC = "GStencil/s + % HBM roofline vs plain sweep; p50/p99 latency mixed load"
+PROFILE = os.path.join(ROOT, "profiles", "tstp_nd_box2d9p_8192_f64.md")
+KERNEL_SOURCES = ["tstp_nd.hpp", "tstp_nd_f64_2d.hip", "jacobi_tstp.hip", "common.hpp",
+                  "kernels.hpp"]
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2010_04868_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def profiled_traffic():
+    """HBM bytes per band launch from the committed rocprof summary, if it was
+    taken on the current kernel sources (else None)."""
+    try:
+        text = open(PROFILE).read()
+    except OSError:
+        return None
+    m = re.search(r"kernel sources hash: `([0-9a-f]+)`", text)
+    t = re.search(r"HBM traffic per band launch \(bytes\): `([0-9.eE+]+)`", text)
+    if not m or not t or m.group(1) != kernel_hash():
+        return None
+    return float(t.group(1))
 
 
 def time_runs(torch, fn, reps):
@@ -45,19 +78,11 @@ def time_runs(torch, fn, reps):
     return e0.elapsed_time(e1) / reps
 
 
-def stencil_ops(p):
-    """Multiplies + adds per point update (canonical order: P products, P-1 sums)."""
-    return 2 * p.order - 1
-
-
 def cpu_baseline(p, budget_s=15.0):
-    """Time the oracle on a bounded number of steps of the same grid."""
-    import numpy as np
-
+    """The oracle as it stands, on a bounded number of steps of the same grid."""
     import oracle
     from paper_2010_04868_amd import inputs
     u0 = inputs.make_grid(p)
-    # one step first, to size the sample to the budget
     t0 = time.perf_counter()
     u = oracle.sweep(u0, p.coeffs, p.shape, p.dependence, p.boundary, 1)
     one = time.perf_counter() - t0
@@ -65,9 +90,68 @@ def cpu_baseline(p, budget_s=15.0):
     t0 = time.perf_counter()
     oracle.sweep(u, p.coeffs, p.shape, p.dependence, p.boundary, steps)
     dt = time.perf_counter() - t0
-    ups = p.updated_points() * steps / dt
-    return {"value": round(ups / 1e9, 4), "unit": "GStencil/s", "cores": 1, "kind": "oracle",
-            "sample": f"{p.dims[0]}x{p.dims[1]} {p.name}, {steps} of {p.T} steps, single thread"}
+    return {"value": round(p.updated_points() * steps / dt / 1e9, 4), "unit": "GStencil/s",
+            "cores": 1, "kind": "oracle",
+            "sample": f"{p.dims[0]}x{p.dims[1]} 2D 9-point box FP64, {steps} of {p.T} steps, "
+                      f"single thread, {dt:.1f} s"}
+
+
+def serving_run(torch, tvs, inputs, n_req, rho, seed=5):
+    """Poisson stream through the server at offered load rho of its capacity."""
+    import numpy as np
+    mix = inputs.serving_mix(n_req, seed=seed, side2d=(64, 1024), side3d=(32, 128),
+                             n1d=(1000, 100000), steps=(10, 200))
+    grids = [inputs.make_grid(r.problem) for r in mix]
+    outs = [np.empty_like(g) for g in grids]
+    total_updates = sum(r.problem.updated_points() * r.problem.T for r in mix)
+
+    def serve(arrivals):
+        srv = tvs.Server(hbm_budget=4 << 30, max_slots=64, chunk_steps=64)
+        try:
+            t_base = time.perf_counter()
+            ids = []
+            for r, g, a in zip(mix, grids, arrivals):
+                delay = a - (time.perf_counter() - t_base)
+                if delay > 0:
+                    time.sleep(delay)
+                ids.append(srv.submit(r.problem, g))
+            stamps = [srv.wait(i, o) for i, o in zip(ids, outs)]
+            st = srv.stats()
+        finally:
+            srv.close()
+        return stamps, st
+
+    # capacity: everything submitted at once
+    stamps, _ = serve([0.0] * len(mix))
+    makespan = max(s[3] for s in stamps) - min(s[0] for s in stamps)
+    capacity_rps = len(mix) / makespan
+    # Poisson arrivals at rho * capacity
+    rng = np.random.default_rng(seed)
+    gaps = rng.exponential(1.0 / (rho * capacity_rps), size=len(mix))
+    arrivals = np.cumsum(gaps) - gaps[0]
+    stamps, st = serve(list(arrivals))
+    lat = np.array([s[3] - s[0] for s in stamps])
+    span = max(s[3] for s in stamps) - min(s[0] for s in stamps)
+    # the same requests one at a time, each on its own, for comparison
+    t0 = time.perf_counter()
+    for r, g in zip(mix, grids):
+        d = torch.from_numpy(g).to("cuda")
+        tvs.Plan.for_problem(r.problem).run(d, r.problem.coeffs, r.problem.T)
+        torch.cuda.synchronize()
+    alone_s = time.perf_counter() - t0
+    return {
+        "requests": len(mix), "offered_load": rho,
+        "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 2),
+        "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 2),
+        "throughput_GStencil_s": round(total_updates / span / 1e9, 2),
+        "capacity_GStencil_s": round(total_updates / makespan / 1e9, 2),
+        "sequential_alone_GStencil_s": round(total_updates / alone_s / 1e9, 2),
+        "chunks": int(st["chunks"]),
+        "mix": "Poisson stream, seed 5: 1D 3-point / 2D 5- or 9-point / 3D 7-point Jacobi and "
+               "2D 5-point Gauss-Seidel; 2D sides log-uniform 64..1024, 3D 32..128, "
+               "1D 1e3..1e5, T uniform 10..200, FP32/FP64 50/50 (the full mix scaled down to "
+               "fit a benchmark run)",
+    }
 
 
 def main():
@@ -75,15 +159,17 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--tuning", default=None, help="schedule override for the time-skewed run")
+    ap.add_argument("--tuning", default=None, help="fixed schedule instead of the autotuner")
     ap.add_argument("--plain-steps", type=int, default=2, help="timed solves of the plain sweep")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=200)
     ap.add_argument("--n", type=int, default=8192)
     ap.add_argument("--T", type=int, default=1000)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU; multi-GPU runs are not part of this build "
-              "(the sharding design is described in DESIGN.md)", file=sys.stderr)
+        print("bench.py measures one GPU; runs on several GPUs are not part of this build "
+              "(how the sweep would shard is described in DESIGN.md)", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -103,36 +189,39 @@ def main():
     copy_gbs = 2 * src.numel() * 8 / (copy_ms / 1e3) / 1e9
     log(f"copy 1 GiB: {copy_ms:.3f} ms = {copy_gbs:.0f} GB/s (read + write)")
     del src, dst
+
     p = inputs.box2d9p(n=args.n, T=args.T)
     u0 = inputs.make_grid(p)
     grid = torch.from_numpy(u0).to("cuda")
     plan = tvs.Plan.for_problem(p, args.tuning)
+    if args.tuning is None:
+        t0 = time.perf_counter()
+        chosen = plan.tune(grid, p.coeffs, 16)
+        log(f"autotuner: {chosen} ({time.perf_counter() - t0:.1f} s)")
     info = plan.info()
     log("plan:", info)
     nu = p.updated_points()
+    eb = 8
 
     # time-skewed solves
     for _ in range(args.warmup):
         plan.run(grid, p.coeffs, p.T)
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
     ms = time_runs(torch, lambda: plan.run(grid, p.coeffs, p.T), args.steps)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
     value = nu * p.T / (ms / 1e3) / 1e9
-    log(f"tstp: {ms:.3f} ms/solve, {value:.1f} GStencil/s (wall {wall:.2f}s)")
+    log(f"tstp: {ms:.3f} ms/solve, {value:.1f} GStencil/s")
 
-    # dominant kernel: one full band (k steps) per launch; two bands per run so
-    # that the result lands back in the caller's buffer without a copy
+    # dominant kernel: one band of k steps per launch (two per run, so that
+    # the result lands in the caller's buffer with no copy)
     k = info["k"]
     band_ms = time_runs(torch, lambda: plan.run(grid, p.coeffs, 2 * k), 10) / 2
     band_updates = nu * k
-    eb = 8 if p.dtype == inputs.F64 else 4
-    alg_bytes = 2 * eb * nu                           # each point read and written once per band
-    achieved_tops = band_updates * stencil_ops(p) / (band_ms / 1e3) / 1e12
+    flops = band_updates * (2 * p.order - 1)       # P products + (P-1) sums per update
+    achieved_tops = flops / (band_ms / 1e3) / 1e12
+    alg_bytes = 2 * eb * nu                          # each point read and written once per band
     achieved_gbs = alg_bytes / (band_ms / 1e3) / 1e9
-    log(f"band kernel: {band_ms:.4f} ms, {achieved_gbs:.0f} GB/s algorithmic, "
-        f"{achieved_tops:.2f} T op/s")
+    log(f"band kernel: {band_ms:.4f} ms, {achieved_tops:.2f} TFLOP/s algorithmic, "
+        f"{achieved_gbs:.0f} GB/s algorithmic")
 
     # plain one-step-per-launch sweep on the same grid
     plain = tvs.Plan.for_problem(p, "method=plain")
@@ -143,7 +232,10 @@ def main():
     plain_gbs = 2 * eb * nu / (step_ms / 1e3) / 1e9
     log(f"plain: {plain_ms:.3f} ms/solve, {plain_value:.1f} GStencil/s, step {step_ms:.4f} ms "
         f"= {plain_gbs:.0f} GB/s")
+    del grid
+    torch.cuda.empty_cache()
 
+    traffic = profiled_traffic()
     out = {
         "metric": METRIC,
         "value": round(value, 2),
@@ -157,7 +249,8 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic: uniform[0,1) PCG64(seed 2), zero Dirichlet border",
-        "config": {"workload": f"2D 9-point box Jacobi {p.dims[0]}x{p.dims[1]} FP64, T={p.T}",
+        "config": {"workload": f"2D 9-point box Jacobi {p.dims[0]}x{p.dims[1]} FP64, "
+                               f"T={p.T}, weights 1/9",
                    "schedule": f"k={info['k']},w={info['tile_w']},l={info['tile_l']},"
                                f"c={info['lane_c']},lanemap={info['lanemap']}",
                    "updated_points": nu},
@@ -169,10 +262,16 @@ def main():
                         "speedup": round(value / plain_value, 3)},
         "roofline": {"bound": "alu", "achieved": round(achieved_tops, 3),
                      "peak": round(ALU_PEAK_TOPS, 2), "unit": "TFLOP/s",
-                     "frac": round(achieved_tops / ALU_PEAK_TOPS, 4), "traffic": None,
-                     "kernel": "tstp_nd (one band)", "kernel_ms": round(band_ms, 4),
+                     "frac": round(achieved_tops / ALU_PEAK_TOPS, 4),
+                     "traffic": traffic,
+                     "kernel": "tstp_nd (one band of k steps)", "kernel_ms": round(band_ms, 4),
+                     "algorithmic_bytes": alg_bytes,
                      "algorithmic_GBs": round(achieved_gbs, 1)},
     }
+    if not args.no_serve:
+        t0 = time.perf_counter()
+        out["serving"] = serving_run(torch, tvs, inputs, args.serve_requests, 0.8)
+        log(f"serving: {out['serving']} ({time.perf_counter() - t0:.1f} s)")
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(p)
     print(json.dumps(out), flush=True)

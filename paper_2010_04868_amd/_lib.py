@@ -91,6 +91,11 @@ def load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is not built; run paper_2010_04868_amd/build.py "
                           "(or __graft_entry__.build())")
+    # One HIP runtime per process: PyTorch ships its own libamdhip64 (same
+    # SONAME as the system one).  Loading torch first makes this library bind
+    # to that runtime, so the device pointers and stream handles torch hands
+    # us belong to the runtime our kernels are launched on.
+    import torch  # noqa: F401
     lib = ctypes.CDLL(LIB_PATH)
     for name, res, args in SIGNATURES:
         fn = getattr(lib, name)

@@ -1,0 +1,171 @@
+"""The C ABI without a GPU: the library loads, exports every function the
+header declares, validates problems with the documented error codes, and
+parses tunings.  The server's scheduling policy is checked with its
+simulated executor (no device calls)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_2010_04868_amd as tvs
+from paper_2010_04868_amd import _lib, inputs
+from paper_2010_04868_amd.inputs import (BOX, DIRICHLET, F32, F64, GAUSS_SEIDEL, JACOBI,
+                                         PERIODIC, STAR)
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "tvstencil.h")
+
+E = {v: k for k, v in _lib.ERRORS.items()}
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(stencil_\w+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported():
+    lib = ctypes.CDLL(_lib.LIB_PATH)
+    names = declared_functions()
+    assert len(names) >= 15
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == {n for n, _, _ in _lib.SIGNATURES}
+
+
+def code_of(fn):
+    with pytest.raises(tvs.StencilError) as ei:
+        fn()
+    return ei.value.code
+
+
+@pytest.mark.parametrize("args,err", [
+    (((8, 8), F64, STAR, 7, JACOBI, DIRICHLET), "TVS_E_ORDER"),
+    (((8, 8), F64, BOX, 5, JACOBI, DIRICHLET), "TVS_E_ORDER"),
+    (((8, 8, 8, 8), F64, STAR, 9, JACOBI, DIRICHLET), "TVS_E_SHAPE"),
+    (((2, 8), F64, STAR, 5, JACOBI, DIRICHLET), "TVS_E_SHAPE"),
+    (((8, 8), 7, STAR, 5, JACOBI, DIRICHLET), "TVS_E_INVALID"),
+    (((8, 8), F64, 3, 5, JACOBI, DIRICHLET), "TVS_E_INVALID"),
+    (((8, 8), F64, STAR, 5, 4, DIRICHLET), "TVS_E_INVALID"),
+    (((8, 8), F64, STAR, 5, JACOBI, 5), "TVS_E_INVALID"),
+    (((8, 8), F64, STAR, 5, GAUSS_SEIDEL, PERIODIC), "TVS_E_UNSUPPORTED"),
+    (((8, 8), F64, STAR, 9, JACOBI, DIRICHLET), "TVS_E_UNSUPPORTED"),   # radius 2 star
+    (((20,), F64, STAR, 5, JACOBI, DIRICHLET), "TVS_E_UNSUPPORTED"),    # radius 2
+    (((8, 8, 8), F64, STAR, 7, GAUSS_SEIDEL, DIRICHLET), "TVS_E_UNSUPPORTED"),
+])
+def test_plan_validation_codes(args, err):
+    assert code_of(lambda: tvs.Plan(*args)) == E[err]
+    msg = _lib.load().stencil_last_error().decode()
+    assert msg
+
+
+@pytest.mark.parametrize("tuning", ["k", "k=x", "method=fast", "bogus=1", "k=-1",
+                                    "method=tstp,k=8,w=64,c=3",
+                                    "method=tstp,k=8,s=3,w=256,c=4"])
+def test_bad_tunings_rejected(tuning):
+    assert code_of(lambda: tvs.Plan((64, 64), F64, BOX, 9, tuning=tuning)) == E["TVS_E_INVALID"]
+
+
+def test_plan_info_reports_schedule():
+    p = tvs.Plan((8192, 8192), F64, BOX, 9)
+    inf = p.info()
+    assert inf["dims"] == (8192, 8192) and inf["radius"] == 1 and inf["method"] == 1
+    assert inf["k"] >= 1 and inf["s"] == 2 and inf["tile_w"] > 2 * inf["k"]
+    q = tvs.Plan((100, 100), F32, STAR, 5, tuning="method=plain")
+    assert q.info()["method"] == 0 and q.info()["k"] == 1
+    r = tvs.Plan((64, 64), F64, STAR, 5, tuning="method=tstp,kern=1,k=8,c=4")
+    assert r.info()["k"] == 8 and r.info()["lane_c"] == 4
+
+
+def test_run_argument_errors_without_device():
+    lib = _lib.load()
+    p = tvs.Plan((16, 16), F64, STAR, 5)
+    c = (ctypes.c_double * 5)(*([0.2] * 5))
+    fake = ctypes.c_void_p(0x1000)
+    assert lib.stencil_run(p.handle, fake, c, -1, None) == E["TVS_E_INVALID"]
+    assert lib.stencil_run(p.handle, None, c, 3, None) == E["TVS_E_INVALID"]
+    assert lib.stencil_run(None, fake, c, 3, None) == E["TVS_E_INVALID"]
+    assert lib.stencil_run(p.handle, fake, c, 0, None) == 0   # T = 0 enqueues nothing
+    assert lib.stencil_batch_run(0, None, None, None, None, None) == 0
+    assert lib.stencil_batch_run(-1, None, None, None, None, None) == E["TVS_E_INVALID"]
+    assert lib.stencil_plan_destroy(None) == 0
+
+
+def test_tuning_cache_roundtrip(tmp_path, monkeypatch):
+    path = tmp_path / "tune.jsonl"
+    key = "nd2:300x200:f64:box9:jacobi:dirichlet"
+    path.write_text('{"key": "%s", "tuning": "method=tstp,k=6,w=256,h=1,l=40,c=4,lanemap=1,kern=0"}\n' % key)
+    monkeypatch.setenv("TVS_TUNE_CACHE", str(path))
+    inf = tvs.Plan((300, 200), F64, BOX, 9).info()
+    assert (inf["k"], inf["tile_w"], inf["tile_l"], inf["lane_c"], inf["lanemap"]) == (6, 256, 40, 4, 1)
+    # another problem keeps the model-based default
+    assert tvs.Plan((301, 200), F64, BOX, 9).info()["k"] == 8
+
+
+# ---------------------------------------------------------------------------
+# server policy with the simulated executor
+# ---------------------------------------------------------------------------
+
+@pytest.fixture
+def sim_server(monkeypatch):
+    monkeypatch.setenv("TVS_SERVER_SIMULATE", "1")
+    made = []
+
+    def make(**kw):
+        s = tvs.Server(**kw)
+        made.append(s)
+        return s
+    yield make
+    for s in made:
+        s.close()
+
+
+def test_server_completes_everything_fifo(sim_server):
+    srv = sim_server(hbm_budget=8 << 20, max_slots=3, chunk_steps=8)
+    reqs = inputs.serving_mix(40, seed=11, side2d=(16, 300), side3d=(8, 40), n1d=(50, 5000),
+                              steps=(1, 60))
+    ids = []
+    for r in reqs:
+        u = inputs.make_grid(r.problem)
+        ids.append((srv.submit(r.problem, u), u))
+    stamps = []
+    for rid, u in ids:
+        out = np.empty_like(u)
+        ts = srv.wait(rid, out)
+        assert np.array_equal(out, u)           # simulated executor returns the input
+        arrival, admit, start, finish = ts
+        assert arrival <= admit <= start <= finish
+        stamps.append(ts)
+    admits = [t[1] for t in stamps]
+    assert admits == sorted(admits)              # admission in arrival order
+    st = srv.stats()
+    assert st["submitted"] == st["admitted"] == st["completed"] == 40
+    assert st["resident"] == 0 and st["bytes_in_use"] == 0
+
+
+def test_server_budget_and_rejection(sim_server):
+    srv = sim_server(hbm_budget=1 << 20, max_slots=64, chunk_steps=4)
+    big = inputs.box2d9p(n=400, T=10)           # 2 x 1.28 MB > 1 MiB
+    with pytest.raises(tvs.StencilError) as ei:
+        srv.submit(big, inputs.make_grid(big))
+    assert ei.value.code == E["TVS_E_BUSY"]
+    small = inputs.box2d9p(n=100, T=10)         # 2 x 80 KB each: 6 fit at once
+    ids = [srv.submit(small, inputs.make_grid(small)) for _ in range(20)]
+    for rid in ids:
+        srv.wait(rid, np.empty((100, 100)))
+    st = srv.stats()
+    assert st["rejected"] == 1 and st["completed"] == 20
+
+
+def test_server_poll_and_unknown_ids(sim_server):
+    srv = sim_server()
+    p = inputs.heat1d(n=1000, T=5)
+    rid = srv.submit(p, inputs.make_grid(p))
+    out = np.empty(1000)
+    while srv.poll(rid, out) is None:
+        pass
+    with pytest.raises(tvs.StencilError) as ei:
+        srv.poll(rid, out)
+    assert ei.value.code == E["TVS_E_NOTFOUND"]
