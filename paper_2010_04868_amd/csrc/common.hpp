@@ -189,6 +189,52 @@ __device__ __forceinline__ void lds_barrier() {
 }
 
 // Periodic / clamped index.
+// Raw buffer access (gfx9 resource layout, stride 0).  An access whose byte
+// offset is not below the resource's size is dropped by the hardware (a
+// store) or returns zero (a load), without touching memory.  Kernels mask
+// lanes and rows that way instead of branching, so every wave of a pipeline
+// issues the same memory instructions in every step and the compiler can
+// count the outstanding ones exactly (a branch that may skip a load or a
+// store forces it to wait for all of them).
+// Offset of a masked lane: far beyond any resource the kernels build (their
+// sizes stay below 2^31 bytes) and safe from wrap-around in the range check.
+constexpr uint32_t kBufOOB = 0x80000000u;
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const void* base, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes,
+                                             0x00020000);
+}
+template <typename T>
+__device__ __forceinline__ T buf_load(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+    static_assert(sizeof(T) == 8 || sizeof(T) == 4, "element size");
+    if constexpr (sizeof(T) == 8)
+        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0));
+    else
+        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, (int)off, 0, 0));
+}
+template <typename T>
+__device__ __forceinline__ void buf_store(__amdgpu_buffer_rsrc_t r, uint32_t off, T v) {
+    static_assert(sizeof(T) == 8 || sizeof(T) == 4, "element size");
+    if constexpr (sizeof(T) == 8) {
+        using V2 = unsigned int __attribute__((ext_vector_type(2)));
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V2, v), r, (int)off, 0, 0);
+    } else {
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), r, (int)off, 0,
+                                              0);
+    }
+}
+
+// Workgroups of a launch are dispatched to the 8 XCDs round robin (block b
+// runs on XCD b mod 8).  This maps block b to a tile index such that every
+// XCD processes one contiguous range of tiles, so tiles that share a halo
+// mostly run on the same XCD and meet in its L2.  It is a bijection on
+// [0, n) for every n.
+__host__ __device__ __forceinline__ int xcd_block(int b, int n) {
+    constexpr int X = 8;
+    const int x = b % X, i = b / X;
+    const int per = n / X, rem = n % X;
+    return x < rem ? x * (per + 1) + i : rem * (per + 1) + (x - rem) * per + i;
+}
+
 __host__ __device__ __forceinline__ int64_t wrap_idx(int64_t i, int64_t n) {
     i %= n;
     return i < 0 ? i + n : i;

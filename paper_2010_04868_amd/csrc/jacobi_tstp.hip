@@ -32,6 +32,11 @@ bool band_geometry(const Problem& p, const Schedule& s, int k, BandGeom* g) {
         *g = r;
         return true;
     }
+    // the LDS pipeline addresses one stream-axis plane through a buffer
+    // resource with 31-bit offsets
+    const int64_t plane_bytes =
+        (p.ndim == 3 ? p.dims[1] * p.dims[2] : p.dims[1]) * (int64_t)p.elem_bytes();
+    if (plane_bytes >= (int64_t(1) << 31)) return false;
     r.C = s.c;
     if (p.ndim == 2 && s.kern == 1 && k == s.k) {
         // register pipeline: a wave is a tile of 64*C columns, 4 tiles per workgroup

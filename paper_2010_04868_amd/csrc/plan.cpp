@@ -217,6 +217,14 @@ Schedule default_schedule(const Problem& p) {
         while (s.h * s.w / s.c * s.k > 512 && s.c < 16) s.c *= 2;
     }
     choose_segment(p, &s);
+    // a grid the band kernels cannot take (e.g. a stream-axis plane of 2 GiB
+    // or more) runs the plain sweep
+    BandGeom g;
+    if (!band_geometry(p, s, s.k, &g)) {
+        Schedule plain;
+        plain.method = TVS_METHOD_PLAIN;
+        return plain;
+    }
     return s;
 }
 

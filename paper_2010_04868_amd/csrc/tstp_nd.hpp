@@ -16,9 +16,11 @@
 // reorganized input vectors are stored for the following outer iterations).
 // Within a plane row, element x of lane group g = x / C sits at
 // (x mod C) * S + g + 1: same-position values of consecutive lanes are
-// contiguous -- the transposed layout of Section 3.3 -- which makes every
-// read and write of the pipeline free of bank conflicts.  One barrier per
-// step separates the writers of one parity from the readers of the other.
+// contiguous -- the transposed layout of Section 3.3.  The planes of one
+// parity are consecutive, PSP elements apart, and S and PSP are padded so
+// that the lanes' reads and writes and the staging accesses spread over the
+// LDS banks (lds_layout.cpp).  One barrier per step separates the writers of
+// one parity from the readers of the other.
 //
 // Level 0 is staged from HBM a few steps ahead; level k goes through its own
 // LDS plane and is stored by all threads one step later, so loads and stores
@@ -47,7 +49,8 @@ struct ArgsNd {
     int Wv, Hv;       // valid extents
     int S;            // LDS sub-row stride (elements); row stride is C*S
     int Wp;           // LDS row stride (elements)
-    int PSP;          // LDS plane stride (elements)
+    int PSP;          // LDS plane stride (elements); plane (level l, parity r)
+                      // starts at (r * (k + 1) + l) * PSP
     int G, Gx, NT;    // lanes per level, lane groups per tile row, threads
     int Lv, Lin;
     int ntx, nty;
@@ -107,6 +110,9 @@ __device__ __forceinline__ void tstp_tile(const T* __restrict__ in, T* __restric
     const int gy_lane = y_org + ly;
     const bool y_border = D == 3 && !PER && (gy_lane == 0 || gy_lane == a.ny - 1);
 
+    // LDS plane of time level l (0..k) and stream-position parity r
+    auto plane = [&](int l, int r) -> T* { return lds + (r * (k + 1) + l) * a.PSP; };
+
     // zero the LDS planes once (pads stay zero; they only feed invalid points)
     if (worker)
         for (int e = tid; e < (k + 1) * 2 * a.PSP; e += a.NT) lds[e] = T(0);
@@ -114,14 +120,18 @@ __device__ __forceinline__ void tstp_tile(const T* __restrict__ in, T* __restric
     // Staging: thread handles elements e = tid + i*NT of a tile plane, both to
     // load level 0 from HBM into LDS and to store level k from LDS to HBM.
     // The LDS position of element (row yl, column xl) is the one the lanes use.
+    // Global accesses go through per-plane buffer resources: a thread without
+    // an element, or without a valid output, gets an out-of-range offset, and
+    // a row outside the segment gets an empty resource, so every step issues
+    // the same loads and stores (no branch around them).
     const int PS = a.H * a.W;
-    int st_lds[NPT], st_g[NPT], st_out[NPT];
+    int st_lds[NPT];
+    uint32_t ld_off[NPT], st_off[NPT];
 #pragma unroll
     for (int i = 0; i < NPT; ++i) {
         const int e = tid + i * a.NT;
         st_lds[i] = -1;
-        st_g[i] = 0;
-        st_out[i] = -1;
+        ld_off[i] = st_off[i] = kBufOOB;
         if (worker && e < PS) {
             const int yl = D == 3 ? e / a.W : 0;
             const int xl = e - yl * a.W;
@@ -129,25 +139,24 @@ __device__ __forceinline__ void tstp_tile(const T* __restrict__ in, T* __restric
             int gxx = PER ? (int)wrap_idx(ox, a.nx) : (int)clamp_idx(ox, a.nx);
             int gyy = D == 3 ? (PER ? (int)wrap_idx(oy, a.ny) : (int)clamp_idx(oy, a.ny)) : 0;
             st_lds[i] = (D == 3 ? (yl + 1) * Wp : 0) + (xl % C) * S + xl / C + 1;
-            st_g[i] = gyy * a.nx + gxx;
+            ld_off[i] = (uint32_t)(gyy * a.nx + gxx) * (uint32_t)sizeof(T);
             const bool valid = xl >= k && xl < a.W - k && ox < a.nx &&
                                (D != 3 || (yl >= k && yl < a.H - k && oy < a.ny));
-            if (valid) st_out[i] = oy * a.nx + ox;
+            if (valid) st_off[i] = (uint32_t)(oy * a.nx + ox) * (uint32_t)sizeof(T);
         }
     }
     const int64_t plane_elems = (int64_t)a.ny * a.nx;
+    const uint32_t plane_bytes = (uint32_t)(plane_elems * (int64_t)sizeof(T));
     auto issue_load = [&](int q, T* dst) {
-        if (q >= a.Lin) return;
         int64_t gz = z_org + q;
         gz = PER ? wrap_idx(gz, a.nz) : clamp_idx(gz, a.nz);
-        const T* src = in + gz * plane_elems;
+        const auto rs = buf_rsrc(in + gz * plane_elems, q < a.Lin ? plane_bytes : 0u);
 #pragma unroll
-        for (int i = 0; i < NPT; ++i)
-            if (st_lds[i] >= 0) dst[i] = src[st_g[i]];
+        for (int i = 0; i < NPT; ++i) dst[i] = buf_load<T>(rs, ld_off[i]);
     };
     auto store_input = [&](int q, const T* v) {
         if (q >= a.Lin) return;
-        T* pl = lds + (q & 1) * a.PSP;  // level 0, parity q&1
+        T* pl = plane(0, q & 1);
 #pragma unroll
         for (int i = 0; i < NPT; ++i)
             if (st_lds[i] >= 0) pl[st_lds[i]] = v[i];
@@ -155,19 +164,22 @@ __device__ __forceinline__ void tstp_tile(const T* __restrict__ in, T* __restric
     // level k emitted tile row q-1-2k at step q-1 into its plane; write it out
     auto store_output = [&](int q) {
         const int row = q - 1 - 2 * k;
-        if (row < k || row >= a.Lin - k) return;
         const int64_t gz = (int64_t)z_org + row;
-        if (gz >= a.nz) return;
-        const T* pl = lds + (k * 2 + ((q - 1) & 1)) * a.PSP;
-        T* o = out + gz * plane_elems;
+        const bool ok = row >= k && row < a.Lin - k && gz < a.nz;
+        const T* pl = plane(k, (q - 1) & 1);
+        const auto rs = buf_rsrc(out + (ok ? gz : 0) * plane_elems, ok ? plane_bytes : 0u);
 #pragma unroll
-        for (int i = 0; i < NPT; ++i)
-            if (st_out[i] >= 0) o[st_out[i]] = pl[st_lds[i]];
+        for (int i = 0; i < NPT; ++i) buf_store<T>(rs, st_off[i], pl[st_lds[i] < 0 ? 0 : st_lds[i]]);
     };
 
     T Sacc[C], Macc[C];
+    // Dirichlet: a fixed border point has the same value at every level, so
+    // its level-j value is level j-1's value at the same point -- the centre
+    // value this lane read one step earlier (stream row p-1).  Keeping those
+    // raw values avoids a global load (and its wait) in the step.
+    T prevc[C];
 #pragma unroll
-    for (int c = 0; c < C; ++c) Sacc[c] = Macc[c] = T(0);
+    for (int c = 0; c < C; ++c) Sacc[c] = Macc[c] = prevc[c] = T(0);
     const T cu = cf.c[0];  // the common weight when UNI
 
     const int row_off = D == 3 ? ly * Wp : 0;  // padded row ly holds tile row ly-1
@@ -186,7 +198,7 @@ __device__ __forceinline__ void tstp_tile(const T* __restrict__ in, T* __restric
         store_output(q);
         const int p = q - 2 * j + 1;  // stream position of the level-(j-1) plane read now
         if (p >= 0 && p < a.Lin) {
-            const T* src = lds + ((j - 1) * 2 + ((q - 1) & 1)) * a.PSP + row_off;
+            const T* src = plane(j - 1, (q - 1) & 1) + row_off;
             // v[r][i]: plane row ly-1+r, tile column lx-1+i (multiplied by the
             // common weight when UNI)
             T v[R][C + 2];
@@ -201,6 +213,9 @@ __device__ __forceinline__ void tstp_tile(const T* __restrict__ in, T* __restric
                     v[r][i] = rs[pos];
                 }
             }
+            T centre[C];
+#pragma unroll
+            for (int c = 0; c < C; ++c) centre[c] = v[MID][1 + c];
             if (UNI) {
 #pragma unroll
                 for (int r = 0; r < R; ++r)
@@ -226,7 +241,7 @@ __device__ __forceinline__ void tstp_tile(const T* __restrict__ in, T* __restric
             const int gz_out = z_org + p - 1;
             const bool z_border = !PER && (gz_out == 0 || gz_out == a.nz - 1);
             const bool emit = p >= 1;
-            T* dst = lds + (j * 2 + (q & 1)) * a.PSP + (D == 3 ? row_off + Wp : 0) + gx + 1;
+            T* dst = plane(j, q & 1) + (D == 3 ? row_off + Wp : 0) + gx + 1;
 #pragma unroll
             for (int c = 0; c < C; ++c) {
                 T f = Macc[c];
@@ -240,13 +255,11 @@ __device__ __forceinline__ void tstp_tile(const T* __restrict__ in, T* __restric
                 if (!PER && border_tile) {
                     // a fixed border point keeps its input value at every level
                     const int gxc = x_org + lx + c;
-                    if ((z_border || y_border || gxc == 0 || gxc == a.nx - 1) && gz_out >= 0 &&
-                        gz_out < a.nz && gxc >= 0 && gxc < a.nx &&
-                        (D != 3 || (gy_lane >= 0 && gy_lane < a.ny)))
-                        f = in[((int64_t)gz_out * a.ny + (D == 3 ? gy_lane : 0)) * a.nx + gxc];
+                    if (z_border || y_border || gxc == 0 || gxc == a.nx - 1) f = prevc[c];
                 }
                 Macc[c] = m;
                 Sacc[c] = s;
+                prevc[c] = centre[c];
                 if (emit) dst[c * S] = f;
             }
         }
@@ -256,12 +269,14 @@ __device__ __forceinline__ void tstp_tile(const T* __restrict__ in, T* __restric
     lds_barrier();  // LDS zeroed
 #pragma unroll
     for (int d = 0; d < DP; ++d) issue_load(d, pre[d]);
-    // level k emits its last row at step Lin+k-1; it is stored one step later
+    // level k emits its last row at step Lin+k-1; it is stored one step later.
+    // Whole groups of DP steps run: the extra steps load and store nothing
+    // (empty resources) and compute nothing (p >= Lin for every level).
     const int Q = a.Lin + k + 1;
     for (int q = 0; q < Q; q += DP) {
         static_for<0, DP>([&](auto dc) {
             constexpr int d = decltype(dc)::value;
-            if (q + d < Q) step(q + d, pre[d]);
+            step(q + d, pre[d]);
         });
     }
 }
@@ -270,29 +285,21 @@ template <typename T, int D, bool BOX, bool PER, int C, int NPT, bool UNI>
 __global__ __launch_bounds__(512) void tstp_nd(const T* __restrict__ in, T* __restrict__ out,
                                                ArgsNd a, Coeffs<T> cf) {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
-    tstp_tile<T, D, BOX, PER, C, NPT, UNI>(in, out, a, cf, blockIdx.x,
+    tstp_tile<T, D, BOX, PER, C, NPT, UNI>(in, out, a, cf, xcd_block(blockIdx.x, gridDim.x),
                                            reinterpret_cast<T*>(smem_raw), threadIdx.x);
 }
 
-// LDS sub-row stride: at least Gx+2, and congruent to 16/C modulo 32/C, so
-// that the 16 lanes of one LDS cycle hit distinct banks both when lanes read
-// their neighbours (consecutive lane groups) and when staging threads write a
-// row in order (consecutive columns, i.e. C sub-rows x 16/C lane groups).
-inline int lds_sub_stride(int Gx, int C) {
-    const int want = 16 / C, mod = 32 / C;
-    int S = Gx + 2;
-    while (S % mod != want % mod) ++S;
-    return S;
-}
+// Paddings S (sub-row stride), Wp = C * S (row stride) and PSP (plane
+// stride) of a band geometry, in elements; see lds_layout.cpp.
+struct LdsLayout {
+    int S, Wp, PSP;
+};
+LdsLayout lds_layout(int D, bool box, int eb, int C, int W, int H, int k, int lanemap, int NT,
+                     int G);
 
-// Plane stride: padded so that lanes of different levels in one 16-lane
-// group (lane map 0) fall on different banks.
-inline int lds_plane_stride(int elems, int k, int lanemap) {
-    int kk = k >= 16 ? 16 : k >= 8 ? 8 : k >= 4 ? 4 : k >= 2 ? 2 : 1;
-    const int want = lanemap == 0 ? 16 / kk : 1;
-    int P = elems;
-    while (P % 16 != want % 16) ++P;
-    return P;
+inline LdsLayout lds_layout(const Problem& p, const BandGeom& g) {
+    return lds_layout(p.ndim, p.shape == TVS_BOX, (int)p.elem_bytes(), g.C, g.W, g.H, g.k,
+                      g.lanemap, g.NT, g.G);
 }
 
 // Kernel arguments of a band (host side).
@@ -308,9 +315,10 @@ inline ArgsNd make_args(const Problem& p, const BandGeom& g) {
     a.Wv = g.Wv;
     a.Hv = g.Hv;
     a.Gx = g.W / g.C;
-    a.S = lds_sub_stride(a.Gx, g.C);
-    a.Wp = g.C * a.S;
-    a.PSP = lds_plane_stride(D == 3 ? (g.H + 2) * a.Wp : a.Wp, g.k, g.lanemap);
+    const LdsLayout lay = lds_layout(p, g);
+    a.S = lay.S;
+    a.Wp = lay.Wp;
+    a.PSP = lay.PSP;
     a.G = g.G;
     a.NT = g.NT;
     a.Lv = g.Lv;
@@ -373,11 +381,7 @@ hipError_t launch_nd_impl(const Problem& p, const BandGeom& g, const T* in, T* o
 
 // LDS bytes a band of this geometry needs (same formula as the launcher).
 inline size_t tstp_nd_lds_bytes(const Problem& p, const BandGeom& g) {
-    const int Gx = g.W / g.C;
-    const int S = nd::lds_sub_stride(Gx, g.C);
-    const int Wp = g.C * S;
-    const int PSP = nd::lds_plane_stride(p.ndim == 3 ? (g.H + 2) * Wp : Wp, g.k, g.lanemap);
-    return (size_t)(g.k + 1) * 2 * PSP * p.elem_bytes();
+    return (size_t)(g.k + 1) * 2 * nd::lds_layout(p, g).PSP * p.elem_bytes();
 }
 
 hipError_t launch_nd_f64_2d(const Problem&, const BandGeom&, const double*, double*,
