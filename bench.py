@@ -64,6 +64,42 @@ def profiled_traffic():
     return float(t.group(1))
 
 
+# name -> (builder, description); builders take (n, T) overrides or None
+WORKLOADS = {
+    "box2d9p": (lambda inp, n, T: inp.box2d9p(**_kw(n, T)), "2D 9-point box Jacobi FP64"),
+    "box2d9p_f32": (lambda inp, n, T: inp.box2d9p(inp.F32, **_kw(n, T)),
+                    "2D 9-point box Jacobi FP32"),
+    "star3d7p": (lambda inp, n, T: inp.star3d7p(**_kw(n, T)), "3D 7-point star Jacobi FP64"),
+    "star3d7p_f32": (lambda inp, n, T: inp.star3d7p(inp.F32, **_kw(n, T)),
+                     "3D 7-point star Jacobi FP32"),
+    "heat1d": (lambda inp, n, T: inp.heat1d(**_kw(n, T)), "1D 3-point Jacobi FP64"),
+    "gs2d5p": (lambda inp, n, T: inp.gs2d5p(**_kw(n, T)), "2D 5-point Gauss-Seidel FP64"),
+}
+
+
+def _kw(n, T):
+    kw = {}
+    if n is not None:
+        kw["n"] = n
+    if T is not None:
+        kw["T"] = T
+    return kw
+
+
+def describe(p, inputs) -> str:
+    kind = {(inputs.STAR, 3): "3-point", (inputs.STAR, 5): "5-point", (inputs.STAR, 7): "7-point",
+            (inputs.BOX, 9): "9-point box"}.get((p.shape, p.order), f"{p.order}-point")
+    dep = "Gauss-Seidel (in place, lexicographic)" if p.dependence == inputs.GAUSS_SEIDEL else \
+        "Jacobi"
+    dims = "x".join(str(d) for d in p.dims)
+    dt = "FP64" if p.dtype == inputs.F64 else "FP32"
+    bnd = "periodic" if p.boundary == inputs.PERIODIC else \
+        ("zero Dirichlet border" if p.zero_border else "fixed Dirichlet ends")
+    w = sorted(set(p.coeffs))
+    wt = "weights " + ("1/9" if w == [1.0 / 9.0] else "/".join(f"{x:g}" for x in p.coeffs))
+    return f"{p.ndim}D {kind} {dep} {dims} {dt}, T={p.T}, {bnd}, {wt}"
+
+
 def time_runs(torch, fn, reps):
     """Average device time (ms) of fn() over reps, with events on the current stream."""
     st = torch.cuda.current_stream()
@@ -76,6 +112,16 @@ def time_runs(torch, fn, reps):
     e1.record(st)
     e1.synchronize()
     return e0.elapsed_time(e1) / reps
+
+
+def kernel_name(p, info, inputs) -> str:
+    if info["method"] == 0:
+        return "plain step"
+    if p.dependence == inputs.GAUSS_SEIDEL:
+        return "gs2d wavefront"
+    if p.ndim == 1:
+        return "tstp1d"
+    return "tstp_reg2d" if info.get("kern", 0) == 1 else "tstp_nd"
 
 
 def cpu_baseline(p, budget_s=15.0):
@@ -92,8 +138,8 @@ def cpu_baseline(p, budget_s=15.0):
     dt = time.perf_counter() - t0
     return {"value": round(p.updated_points() * steps / dt / 1e9, 4), "unit": "GStencil/s",
             "cores": 1, "kind": "oracle",
-            "sample": f"{p.dims[0]}x{p.dims[1]} 2D 9-point box FP64, {steps} of {p.T} steps, "
-                      f"single thread, {dt:.1f} s"}
+            "sample": f"{describe(p, inputs)}: {steps} of {p.T} steps, single thread, "
+                      f"{dt:.1f} s"}
 
 
 def serving_run(torch, tvs, inputs, n_req, rho, seed=5):
@@ -164,8 +210,10 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=200)
-    ap.add_argument("--n", type=int, default=8192)
-    ap.add_argument("--T", type=int, default=1000)
+    ap.add_argument("--workload", default="box2d9p", choices=sorted(WORKLOADS),
+                    help="problem to time (default: the headline 2D 9-point box FP64)")
+    ap.add_argument("--n", type=int, default=None, help="grid side (default: the workload's)")
+    ap.add_argument("--T", type=int, default=None, help="time steps (default: the workload's)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU; runs on several GPUs are not part of this build "
@@ -190,7 +238,7 @@ def main():
     log(f"copy 1 GiB: {copy_ms:.3f} ms = {copy_gbs:.0f} GB/s (read + write)")
     del src, dst
 
-    p = inputs.box2d9p(n=args.n, T=args.T)
+    p = WORKLOADS[args.workload][0](inputs, args.n, args.T)
     u0 = inputs.make_grid(p)
     grid = torch.from_numpy(u0).to("cuda")
     plan = tvs.Plan.for_problem(p, args.tuning)
@@ -201,7 +249,7 @@ def main():
     info = plan.info()
     log("plan:", info)
     nu = p.updated_points()
-    eb = 8
+    eb = 8 if p.dtype == inputs.F64 else 4
 
     # time-skewed solves
     for _ in range(args.warmup):
@@ -235,7 +283,7 @@ def main():
     del grid
     torch.cuda.empty_cache()
 
-    traffic = profiled_traffic()
+    traffic = profiled_traffic() if args.workload == "box2d9p" and args.n is None else None
     out = {
         "metric": METRIC,
         "value": round(value, 2),
@@ -247,12 +295,10 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
-        "data": "synthetic: uniform[0,1) PCG64(seed 2), zero Dirichlet border",
-        "config": {"workload": f"2D 9-point box Jacobi {p.dims[0]}x{p.dims[1]} FP64, "
-                               f"T={p.T}, weights 1/9",
-                   "schedule": f"k={info['k']},w={info['tile_w']},l={info['tile_l']},"
-                               f"c={info['lane_c']},lanemap={info['lanemap']}",
+        "dtype": "f64" if eb == 8 else "f32",
+        "data": f"synthetic: uniform[0,1) PCG64(seed {p.seed})",
+        "config": {"workload": describe(p, inputs),
+                   "schedule": plan.tuning(),
                    "updated_points": nu},
         "hbm_effective_frac": round(value * 2 * eb / HBM_PEAK_GBS, 4),
         "copy_GBs": round(copy_gbs, 1),
@@ -264,11 +310,12 @@ def main():
                      "peak": round(ALU_PEAK_TOPS, 2), "unit": "TFLOP/s",
                      "frac": round(achieved_tops / ALU_PEAK_TOPS, 4),
                      "traffic": traffic,
-                     "kernel": "tstp_nd (one band of k steps)", "kernel_ms": round(band_ms, 4),
+                     "kernel": f"{kernel_name(p, info, inputs)} (one launch of k steps)",
+                     "kernel_ms": round(band_ms, 4),
                      "algorithmic_bytes": alg_bytes,
                      "algorithmic_GBs": round(achieved_gbs, 1)},
     }
-    if not args.no_serve:
+    if not args.no_serve and args.workload == "box2d9p":
         t0 = time.perf_counter()
         out["serving"] = serving_run(torch, tvs, inputs, args.serve_requests, 0.8)
         log(f"serving: {out['serving']} ({time.perf_counter() - t0:.1f} s)")

@@ -94,6 +94,9 @@ typedef struct tvs_plan_info {
     int lanemap;       /* 0 = successive levels in successive lanes,
                           1 = successive levels in successive waves */
     size_t scratch_bytes; /* device memory the plan owns */
+    int pl;            /* 1D: lanes per pipeline (16 or 64) */
+    int kern;          /* 2D Jacobi: 0 = LDS level planes, 1 = register pipeline */
+    char tuning[160];  /* the schedule as a tuning string that stencil_plan accepts */
 } tvs_plan_info;
 
 /*
@@ -108,7 +111,7 @@ typedef struct tvs_plan_info {
  *   boundary    TVS_DIRICHLET or TVS_PERIODIC (Gauss-Seidel: Dirichlet only)
  *   tuning      NULL: the tuned default (autotune cache, else a model-based
  *               choice); otherwise "key=value" pairs separated by commas:
- *               method=plain|tstp, k=, s=, w=, h=, l=, c=, lanemap=
+ *               method=plain|tstp, k=, s=, w=, h=, l=, c=, lanemap=, pl=, kern=
  * The plan is created without touching the device; device scratch (the
  * Jacobi second buffer) is allocated at the first run and freed by
  * stencil_plan_destroy.  *out is set only on success.

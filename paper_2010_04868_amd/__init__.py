@@ -84,7 +84,12 @@ class Plan:
         check(load().stencil_plan_info(self._h, ctypes.byref(inf)))
         out = {f: getattr(inf, f) for f, _ in inf._fields_}
         out["dims"] = tuple(inf.dims[: inf.ndim])
+        out["tuning"] = inf.tuning.decode()
         return out
+
+    def tuning(self) -> str:
+        """The plan's schedule as a tuning string (accepted by ``Plan(..., tuning=)``)."""
+        return self.info()["tuning"]
 
     def run(self, grid, coeffs: Sequence[float], T: int, stream=None) -> None:
         """Advance the device tensor ``grid`` by T steps, asynchronously on ``stream``."""

@@ -31,6 +31,7 @@ class PlanInfo(ctypes.Structure):
         ("k", ctypes.c_int), ("s", ctypes.c_int), ("tile_w", ctypes.c_int),
         ("tile_h", ctypes.c_int), ("tile_l", ctypes.c_int), ("lane_c", ctypes.c_int),
         ("lanemap", ctypes.c_int), ("scratch_bytes", ctypes.c_size_t),
+        ("pl", ctypes.c_int), ("kern", ctypes.c_int), ("tuning", ctypes.c_char * 160),
     ]
 
 

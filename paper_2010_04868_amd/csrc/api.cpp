@@ -1,4 +1,5 @@
 // C ABI: plans, single runs, the one-call form and plan introspection.
+#include <cstdio>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -180,6 +181,9 @@ int stencil_plan_info(const tvs_plan* p, tvs_plan_info* info) {
     info->lane_c = p->sched.c;
     info->lanemap = p->sched.lanemap;
     info->scratch_bytes = p->scratch_bytes + p->gs_work_bytes;
+    info->pl = p->sched.pl;
+    info->kern = p->sched.kern;
+    std::snprintf(info->tuning, sizeof info->tuning, "%s", format_tuning(p->prob, p->sched).c_str());
     return TVS_OK;
 }
 

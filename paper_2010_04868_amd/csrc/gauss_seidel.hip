@@ -35,7 +35,13 @@ namespace tvs {
 namespace {
 
 constexpr int kRows = 64;        // rows per band (one wave)
-constexpr int kBlock = 8;        // steps between dependency checks / progress updates
+constexpr int kBlock = 8;        // steps whose loads are issued together
+// Steps between dependency checks and progress updates.  Crossing the XCDs'
+// separate L2 caches makes every agent-scope acquire and release expensive
+// (an L2 invalidate or write-back), so they are done once per kSync steps;
+// a dependent item then trails its producer by about kSync columns.
+constexpr int kSync = 64;
+static_assert(kSync % kBlock == 0, "sync interval");
 constexpr long long kSpinLimit = 1ll << 22;  // ~seconds: far beyond any legitimate wait
 
 struct GsArgs {
@@ -49,14 +55,15 @@ struct GsArgs {
     int* progress;  // [sweeps][nb]
 };
 
-__device__ __forceinline__ int load_acquire(const int* p) {
-    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+__device__ __forceinline__ int load_relaxed(const int* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Wait until *p >= need (or the launch has been aborted).  Uniform per wave.
+// Relaxed polling: the caller issues one acquire fence after all its waits.
 __device__ __forceinline__ void wait_at_least(const int* p, int need, int* status) {
     long long spins = 0;
-    while (load_acquire(p) < need) {
+    while (load_relaxed(p) < need) {
         if (__hip_atomic_load(status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return;
         if (++spins > kSpinLimit) {
             __hip_atomic_store(status, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -121,12 +128,15 @@ __global__ __launch_bounds__(64) void gs2d(T* grid, GsArgs a, Coeffs<T> cf) {
         T SWv = row_s[0], Sv = SWv, SEv = SWv;
         T out = 0;
         const int U = a.ncols + 2 + SIG * L;  // steps: column c = u - 1 - SIG*lane in [-1, ncols]
-        for (int u0 = 0; u0 < U; u0 += kBlock) {
-            // columns the leading lane (lane 0) reaches in this block
-            const int cmax = u0 + kBlock - 2;
-            if (prog_prev) wait_at_least(prog_prev, min(a.ncols, cmax + 2), a.status);
-            if (prog_south) wait_at_least(prog_south, min(a.ncols, cmax + 2), a.status);
-            if (prog_north) wait_at_least(prog_north, min(a.ncols, cmax + SIG), a.status);
+        for (int us = 0; us < U; us += kSync) {
+          // columns the leading lane (lane 0) reaches in this interval
+          const int cmax = us + kSync - 2;
+          if (prog_prev) wait_at_least(prog_prev, min(a.ncols, cmax + 2), a.status);
+          if (prog_south) wait_at_least(prog_south, min(a.ncols, cmax + 2), a.status);
+          if (prog_north) wait_at_least(prog_north, min(a.ncols, cmax + SIG), a.status);
+          // the producers' rows written before their progress stores are visible now
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+          for (int u0 = us; u0 < us + kSync && u0 < U; u0 += kBlock) {
             T e_in[kBlock], se_in[kBlock], n_in[kBlock];
 #pragma unroll
             for (int m = 0; m < kBlock; ++m) {
@@ -186,10 +196,11 @@ __global__ __launch_bounds__(64) void gs2d(T* grid, GsArgs a, Coeffs<T> cf) {
                     out = r;
                 }
             }
-            // publish the columns completed on the band's last row
-            const int done = min(a.ncols, max(0, u0 + kBlock - 1 - SIG * L));
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-            if (lane == 0) __hip_atomic_store(prog_self, done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          }
+          // publish the columns completed on the band's last row
+          const int done = min(a.ncols, max(0, us + kSync - 1 - SIG * L));
+          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+          if (lane == 0) __hip_atomic_store(prog_self, done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
         if (lane == 0) __hip_atomic_store(prog_self, a.ncols, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);

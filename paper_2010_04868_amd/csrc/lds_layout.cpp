@@ -2,14 +2,17 @@
 // LDS address streams against the bank structure.
 //
 // Bank model of gfx950's LDS, as measured with SQ_LDS_BANK_CONFLICT on
-// in-bounds read patterns: a wavefront's ds_read/ds_write is served 32 lanes
-// per cycle, in lane order, and two lanes of one cycle conflict when their
-// element indices are equal modulo 32 but the elements differ (equal
-// elements broadcast) -- for 4-byte and for 8-byte elements alike (64 banks
-// of 4 bytes serve 32 8-byte lanes).  Conflicting lanes serialise.  The kernel's layout has two
-// free paddings: the sub-row stride S (distance between the C sub-rows of a
-// plane row, the transposed layout) and the plane stride PSP (distance
-// between the LDS planes of successive time levels).  For every candidate
+// in-bounds access patterns: an LDS instruction is served a group of lanes
+// per cycle, in lane order, and two lanes of one group conflict when their
+// element indices are equal modulo the group's slot count but the elements
+// differ (equal elements broadcast); conflicting lanes serialise.
+//   ds_read_b64          32 lanes per cycle, slot = element mod 32
+//   ds_write_b64         16 lanes per cycle, slot = element mod 16
+//   ds_read/write_b32    32 lanes per cycle, slot = element mod 32
+// The kernel's layout has two free paddings: the sub-row stride S (distance
+// between the C sub-rows of a plane row, the transposed layout) and the
+// plane stride PSP (distance between the LDS planes of successive time
+// levels).  For every candidate
 // pair this file replays, for every wave of a workgroup, the addresses the
 // kernel computes (level-plane reads and writes of the lanes, staging writes
 // of level 0 and staging reads of level k) and keeps the pair with the
@@ -28,8 +31,12 @@ namespace nd {
 
 namespace {
 
-constexpr int kLanesPerCycle = 32;
-constexpr int kSlots = 32;  // element index modulo this picks the bank (group)
+struct BankRule {
+    int lanes, slots;
+};
+BankRule read_rule(int) { return {32, 32}; }
+BankRule write_rule(int eb) { return eb == 8 ? BankRule{16, 16} : BankRule{32, 32}; }
+constexpr int kPeriod = 32;  // paddings repeat their bank behaviour with this period
 
 // An LDS address as a linear form in the two paddings: a = cs*S + cp*PSP + c0.
 struct Lin {
@@ -43,18 +50,20 @@ struct Lin {
 struct Access {
     std::vector<std::vector<Lin>> cycles;
     std::vector<int> weight;
+    std::vector<int> slots;
 };
 
-Access replay(int D, bool box, int C, int W, int H, int k, int lanemap, int NT, int G) {
+Access replay(int D, bool box, int eb, int C, int W, int H, int k, int lanemap, int NT,
+              int G) {
     const int Gx = W / C;
-    const int lpc = kLanesPerCycle;
     const int R = D == 3 ? 3 : 1, MID = D == 3 ? 1 : 0;
     const int nwaves = (NT + 63) / 64;
     const int PS = H * W;
     const int npt = (PS + NT - 1) / NT;
     Access acc;
     // one wave-wide instruction: lane l's form, or nothing if inactive
-    auto emit = [&](const std::vector<std::pair<bool, Lin>>& lanes, int weight) {
+    auto emit = [&](const std::vector<std::pair<bool, Lin>>& lanes, int weight, BankRule rule) {
+        const size_t lpc = (size_t)rule.lanes;
         for (size_t c0 = 0; c0 < lanes.size(); c0 += lpc) {
             std::vector<Lin> u;
             for (size_t l = c0; l < c0 + lpc && l < lanes.size(); ++l) {
@@ -66,6 +75,7 @@ Access replay(int D, bool box, int C, int W, int H, int k, int lanemap, int NT, 
             if (!u.empty()) {
                 acc.cycles.push_back(u);
                 acc.weight.push_back(weight);
+                acc.slots.push_back(rule.slots);
             }
         }
     };
@@ -103,7 +113,7 @@ Access replay(int D, bool box, int C, int W, int H, int k, int lanemap, int NT, 
                     }
                     lanes[l].second = a;
                 }
-                emit(lanes, 1);
+                emit(lanes, 1, read_rule(eb));
             }
         // lane writes of the level-j plane: j*PSP + (ly+1)*Wp (3D) + gx + 1 + c*S
         for (int c = 0; c < C; ++c) {
@@ -116,9 +126,10 @@ Access replay(int D, bool box, int C, int W, int H, int k, int lanemap, int NT, 
                 const int ly = D == 3 ? g / Gx : 0, gx = g - ly * Gx;
                 lanes[l].second = Lin{(D == 3 ? C * (ly + 1) : 0) + c, j, gx + 1};
             }
-            emit(lanes, 1);
+            emit(lanes, 1, write_rule(eb));
         }
         // staging: level-0 writes and level-k reads use the same addresses
+        // (every thread reads for the level-k store, also without an element)
         for (int i = 0; i < npt; ++i) {
             for (int l = 0; l < 64; ++l) {
                 const int tid = w * 64 + l;
@@ -128,17 +139,19 @@ Access replay(int D, bool box, int C, int W, int H, int k, int lanemap, int NT, 
                 const int yl = D == 3 ? e / W : 0, xl = e - yl * W;
                 lanes[l].second = Lin{(D == 3 ? C * (yl + 1) : 0) + xl % C, 0, xl / C + 1};
             }
-            emit(lanes, 2);
+            emit(lanes, 1, write_rule(eb));
+            emit(lanes, 1, read_rule(eb));
         }
     }
     return acc;
 }
 
 // LDS cycles of all accesses for one choice of paddings.
-int64_t cost(const Access& acc, int slots, int S, int PSP) {
+int64_t cost(const Access& acc, int S, int PSP) {
     int64_t total = 0;
     int count[64];
     for (size_t c = 0; c < acc.cycles.size(); ++c) {
+        const int slots = acc.slots[c];
         for (int q = 0; q < slots; ++q) count[q] = 0;
         int deg = 0;
         for (const Lin& a : acc.cycles[c]) {
@@ -163,9 +176,9 @@ LdsLayout lds_layout(int D, bool box, int eb, int C, int W, int H, int k, int la
         auto it = g_cache.find(key);
         if (it != g_cache.end()) return it->second;
     }
-    const Access acc = replay(D, box, C, W, H, k, lanemap, NT, G);
+    const Access acc = replay(D, box, eb, C, W, H, k, lanemap, NT, G);
     const int Gx = W / C;
-    const int period = kSlots;
+    const int period = kPeriod;
     // Padding must not cost occupancy: workgroups per CU are limited by waves
     // (four per SIMD at the kernel's register use) and by LDS; keep only
     // layouts that fit as many workgroups as the unpadded one.
@@ -185,7 +198,7 @@ LdsLayout lds_layout(int D, bool box, int eb, int C, int W, int H, int k, int la
         const int base = plane_base(S);
         for (int PSP = base; PSP < base + period; ++PSP) {
             if (occupancy(PSP) < occ0) break;
-            const int64_t c = cost(acc, period, S, PSP);
+            const int64_t c = cost(acc, S, PSP);
             if (best_cost < 0 || c < best_cost) {
                 best_cost = c;
                 best = LdsLayout{S, C * S, PSP};

@@ -37,6 +37,8 @@
 // so this changes no bit.  The result is bit-identical to the naive sweep.
 #pragma once
 
+#include <type_traits>
+
 #include "kernels.hpp"
 
 namespace tvs {
@@ -154,24 +156,28 @@ __device__ __forceinline__ void tstp_tile(const T* __restrict__ in, T* __restric
 #pragma unroll
         for (int i = 0; i < NPT; ++i) dst[i] = buf_load<T>(rs, ld_off[i]);
     };
-    auto store_input = [&](int q, const T* v) {
+    // par: parity of q, known at compile time in the unrolled step loop
+    auto store_input = [&](int q, const T* v, int par) {
         if (q >= a.Lin) return;
-        T* pl = plane(0, q & 1);
+        T* pl = plane(0, par);
 #pragma unroll
         for (int i = 0; i < NPT; ++i)
             if (st_lds[i] >= 0) pl[st_lds[i]] = v[i];
     };
     // level k emitted tile row q-1-2k at step q-1 into its plane; write it out
-    auto store_output = [&](int q) {
+    auto store_output = [&](int q, int par) {
         const int row = q - 1 - 2 * k;
         const int64_t gz = (int64_t)z_org + row;
         const bool ok = row >= k && row < a.Lin - k && gz < a.nz;
-        const T* pl = plane(k, (q - 1) & 1);
+        const T* pl = plane(k, par ^ 1);
         const auto rs = buf_rsrc(out + (ok ? gz : 0) * plane_elems, ok ? plane_bytes : 0u);
 #pragma unroll
         for (int i = 0; i < NPT; ++i) buf_store<T>(rs, st_off[i], pl[st_lds[i] < 0 ? 0 : st_lds[i]]);
     };
 
+    // running sums of a lane's points: Macc lacks the terms of the stencil
+    // row ahead (it becomes this step's output), Sacc lacks the centre and
+    // ahead rows
     T Sacc[C], Macc[C];
     // Dirichlet: a fixed border point has the same value at every level, so
     // its level-j value is level j-1's value at the same point -- the centre
@@ -192,13 +198,16 @@ __device__ __forceinline__ void tstp_tile(const T* __restrict__ in, T* __restric
 #pragma unroll
         for (int i = 0; i < NPT; ++i) pre[d][i] = T(0);
 
-    auto step = [&](int q, T* pr) {
-        store_input(q, pr);
+    // BT: this tile touches a fixed Dirichlet border (uniform per workgroup)
+    auto step = [&](int q, T* pr, auto bt, auto dc) {
+        constexpr bool BT = !PER && decltype(bt)::value;
+        constexpr int par = decltype(dc)::value & 1;  // q & 1
+        store_input(q, pr, par);
         issue_load(q + DP, pr);
-        store_output(q);
+        store_output(q, par);
         const int p = q - 2 * j + 1;  // stream position of the level-(j-1) plane read now
         if (p >= 0 && p < a.Lin) {
-            const T* src = plane(j - 1, (q - 1) & 1) + row_off;
+            const T* src = plane(j - 1, par ^ 1) + row_off;
             // v[r][i]: plane row ly-1+r, tile column lx-1+i (multiplied by the
             // common weight when UNI)
             T v[R][C + 2];
@@ -214,8 +223,10 @@ __device__ __forceinline__ void tstp_tile(const T* __restrict__ in, T* __restric
                 }
             }
             T centre[C];
+            if constexpr (BT) {
 #pragma unroll
-            for (int c = 0; c < C; ++c) centre[c] = v[MID][1 + c];
+                for (int c = 0; c < C; ++c) centre[c] = v[MID][1 + c];
+            }
             if (UNI) {
 #pragma unroll
                 for (int r = 0; r < R; ++r)
@@ -241,7 +252,7 @@ __device__ __forceinline__ void tstp_tile(const T* __restrict__ in, T* __restric
             const int gz_out = z_org + p - 1;
             const bool z_border = !PER && (gz_out == 0 || gz_out == a.nz - 1);
             const bool emit = p >= 1;
-            T* dst = plane(j, q & 1) + (D == 3 ? row_off + Wp : 0) + gx + 1;
+            T* dst = plane(j, par) + (D == 3 ? row_off + Wp : 0) + gx + 1;
 #pragma unroll
             for (int c = 0; c < C; ++c) {
                 T f = Macc[c];
@@ -252,15 +263,18 @@ __device__ __forceinline__ void tstp_tile(const T* __restrict__ in, T* __restric
                 static_for<gm_b, gm_e>([&](auto qc) {
                     s = add(s, qc, c, decltype(qc)::value == gm_b);
                 });
-                if (!PER && border_tile) {
-                    // a fixed border point keeps its input value at every level
-                    const int gxc = x_org + lx + c;
-                    if (z_border || y_border || gxc == 0 || gxc == a.nx - 1) f = prevc[c];
-                }
                 Macc[c] = m;
                 Sacc[c] = s;
-                prevc[c] = centre[c];
                 if (emit) dst[c * S] = f;
+                if constexpr (BT) {
+                    // a fixed border point keeps its input value at every level:
+                    // its lane overwrites the stored sum (a second, masked LDS
+                    // store, so that the sum itself is computed unconditionally)
+                    const int gxc = x_org + lx + c;
+                    const bool fixed = z_border || y_border || gxc == 0 || gxc == a.nx - 1;
+                    if (emit && fixed) dst[c * S] = prevc[c];
+                    prevc[c] = centre[c];
+                }
             }
         }
         lds_barrier();
@@ -270,15 +284,25 @@ __device__ __forceinline__ void tstp_tile(const T* __restrict__ in, T* __restric
 #pragma unroll
     for (int d = 0; d < DP; ++d) issue_load(d, pre[d]);
     // level k emits its last row at step Lin+k-1; it is stored one step later.
-    // Whole groups of DP steps run: the extra steps load and store nothing
-    // (empty resources) and compute nothing (p >= Lin for every level).
+    // The loop body is DP steps, so that the prefetch slot and the plane
+    // parity of every step are compile-time constants.  Whole groups run:
+    // the extra steps load and store nothing (empty resources) and compute
+    // nothing (p >= Lin for every level).
+    static_assert(DP % 2 == 0, "even unroll: the parity of a step is its slot's");
     const int Q = a.Lin + k + 1;
-    for (int q = 0; q < Q; q += DP) {
-        static_for<0, DP>([&](auto dc) {
-            constexpr int d = decltype(dc)::value;
-            step(q + d, pre[d]);
-        });
-    }
+    auto run = [&](auto bt) {
+        for (int q = 0; q < Q; q += DP) {
+            static_for<0, DP>([&](auto dc) {
+                constexpr int d = decltype(dc)::value;
+                step(q + d, pre[d], bt, dc);
+            });
+        }
+    };
+    // interior tiles, the vast majority, carry no border code at all
+    if (!PER && border_tile)
+        run(std::true_type{});
+    else
+        run(std::false_type{});
 }
 
 template <typename T, int D, bool BOX, bool PER, int C, int NPT, bool UNI>

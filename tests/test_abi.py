@@ -76,7 +76,32 @@ def test_plan_info_reports_schedule():
     q = tvs.Plan((100, 100), F32, STAR, 5, tuning="method=plain")
     assert q.info()["method"] == 0 and q.info()["k"] == 1
     r = tvs.Plan((64, 64), F64, STAR, 5, tuning="method=tstp,kern=1,k=8,c=4")
-    assert r.info()["k"] == 8 and r.info()["lane_c"] == 4
+    assert r.info()["k"] == 8 and r.info()["lane_c"] == 4 and r.info()["kern"] == 1
+
+
+@pytest.mark.parametrize("dims,shape,order,dep", [
+    ((8192, 8192), BOX, 9, 0), ((512, 512, 512), STAR, 7, 0), ((100000,), STAR, 3, 0),
+    ((4096, 4096), STAR, 5, 1), ((100, 100), STAR, 5, 0)])
+def test_tuning_string_roundtrips(dims, shape, order, dep):
+    """The schedule a plan reports re-creates exactly that schedule."""
+    a = tvs.Plan(dims, F64, shape, order, dep)
+    t = a.tuning()
+    assert t.startswith("method=")
+    b = tvs.Plan(dims, F64, shape, order, dep, tuning=t)
+    ia, ib = a.info(), b.info()
+    for f in ("method", "k", "s", "tile_w", "tile_h", "tile_l", "lane_c", "lanemap", "pl", "kern",
+              "tuning"):
+        assert ia[f] == ib[f], f
+
+
+def test_huge_plane_runs_plain():
+    """A 3D grid whose stream-axis plane is 2 GiB or more cannot use the band
+    kernels (31-bit plane offsets); the default schedule is then the plain sweep,
+    and an explicit band schedule is rejected."""
+    p = tvs.Plan((3, 16384, 16384), F64, STAR, 7)
+    assert p.info()["method"] == 0
+    assert code_of(lambda: tvs.Plan((3, 16384, 16384), F64, STAR, 7,
+                                    tuning="method=tstp,k=2,w=64,h=32,c=8")) == E["TVS_E_INVALID"]
 
 
 def test_run_argument_errors_without_device():
