@@ -31,6 +31,7 @@ void fill_coeffs(const Problem& p, const double* c, CoeffBuf* out) {
 }
 
 int ensure_scratch(tvs_plan* p) {
+    if (p->external_scratch) return TVS_OK;
     if (p->prob.dependence == TVS_JACOBI) {
         const size_t need = p->prob.bytes();
         if (p->scratch_bytes < need) {
@@ -190,9 +191,11 @@ int stencil_plan_info(const tvs_plan* p, tvs_plan_info* info) {
 int stencil_plan_destroy(tvs_plan* p) {
     clear_error();
     if (!p) return TVS_OK;
-    if (p->scratch || p->gs_work) (void)hipDeviceSynchronize();
-    if (p->scratch) (void)hipFree(p->scratch);
-    if (p->gs_work) (void)hipFree(p->gs_work);
+    if (!p->external_scratch) {
+        if (p->scratch || p->gs_work) (void)hipDeviceSynchronize();
+        if (p->scratch) (void)hipFree(p->scratch);
+        if (p->gs_work) (void)hipFree(p->gs_work);
+    }
     if (p->gs_status_host) (void)hipHostFree(p->gs_status_host);
     if (p->gs_status_event) (void)hipEventDestroy(p->gs_status_event);
     graph_cache_drop(p);

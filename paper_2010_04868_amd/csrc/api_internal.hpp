@@ -12,6 +12,7 @@ struct tvs_plan {
     size_t scratch_bytes = 0;
     void* gs_work = nullptr;  // Gauss-Seidel ticket, status word, progress counters
     size_t gs_work_bytes = 0;
+    bool external_scratch = false;  // scratch/gs_work lent by the owner (server arena)
     int* gs_status_host = nullptr;  // pinned copy of the status word
     hipEvent_t gs_status_event = nullptr;
 };
@@ -40,5 +41,19 @@ std::string problem_key(const Problem& p);
 
 // Graph cache of a plan (captured launch sequences).
 void graph_cache_drop(tvs_plan* p);
+
+// Device work-list buffer and its pinned host staging, kept by a caller that
+// issues many batches (the server), so that a batch allocates nothing.
+struct BatchBuffers {
+    void* dev = nullptr;
+    void* host = nullptr;
+    size_t capacity = 0;
+};
+
+// Enqueue one batch (stencil_batch_run's work).  With ext the work lists go
+// into ext asynchronously and nothing is waited for; otherwise they are
+// allocated per call (use_graph: captured and cached per layout).
+int batch_run(int n, tvs_plan* const* plans, void* const* grids, const double* const* coeffs,
+              const int64_t* T, hipStream_t st, bool use_graph, BatchBuffers* ext);
 
 }  // namespace tvs

@@ -203,11 +203,15 @@ int build_group(const std::vector<Member>& ms, int ndim, std::vector<GridNd<T>>*
     return TVS_OK;
 }
 
-// One group, prepared on the host: the device work list is uploaded before
-// any stream work is enqueued, so the launches can be captured in a graph.
+// One group, prepared on the host.  Its work list ([items | grids]) is
+// built as a host image and then uploaded either into memory the group owns
+// (synchronously, before any stream work, so that the launches can be
+// captured in a graph) or into caller-provided buffers (asynchronously).
 struct GroupLaunch {
     Variant v;
     void* dev = nullptr;  // [items | grids]
+    bool owned = false;   // dev was allocated for this group
+    std::vector<unsigned char> image;
     size_t lds = 0;
     std::vector<int> round_begin;  // item offset of each round, plus the end
     size_t off_grids = 0;
@@ -231,15 +235,11 @@ int prepare_group(const Variant& v, const std::vector<Member>& ms, GroupLaunch* 
     const size_t grid_bytes =
         v.ndim == 1 ? g1d.size() * sizeof(Grid1d<T>) : gnd.size() * sizeof(GridNd<T>);
     const size_t total = gl->off_grids + grid_bytes;
-    std::vector<unsigned char> host(total, 0);
+    std::vector<unsigned char>& host = gl->image;
+    host.assign(total, 0);
     std::memcpy(host.data(), items.data(), items.size() * sizeof(BatchItem));
     if (v.ndim == 1) std::memcpy(host.data() + gl->off_grids, g1d.data(), grid_bytes);
     else std::memcpy(host.data() + gl->off_grids, gnd.data(), grid_bytes);
-    if (hipMalloc(&gl->dev, total) != hipSuccess) {
-        gl->dev = nullptr;
-        return set_error(TVS_E_NOMEM, "hipMalloc of the batch work list failed");
-    }
-    TVS_HIP_TRY(hipMemcpy(gl->dev, host.data(), total, hipMemcpyHostToDevice));
     for (int i : odd) {
         gl->copies.emplace_back(ms[i].plan->scratch, ms[i].grid);
         gl->copy_elems.push_back(ms[i].plan->prob.elems());
@@ -249,7 +249,7 @@ int prepare_group(const Variant& v, const std::vector<Member>& ms, GroupLaunch* 
 
 template <typename T>
 int launch_group(const GroupLaunch& gl, hipStream_t st) {
-    if (!gl.dev) return TVS_OK;
+    if (!gl.dev || gl.image.empty()) return TVS_OK;
     const Variant& v = gl.v;
     const int rounds = (int)gl.round_begin.size() - 1;
     for (int b = 0; b < rounds; ++b) {
@@ -325,8 +325,60 @@ struct BatchPlan {
 
 void free_batch(BatchPlan* bp) {
     for (auto& g : bp->groups)
-        if (g.dev) (void)hipFree(g.dev);
+        if (g.dev && g.owned) (void)hipFree(g.dev);
     bp->groups.clear();
+}
+
+// Upload the work lists of a prepared batch.  Without ext: one allocation per
+// group, synchronous copies.  With ext: all lists packed into ext's pinned
+// host staging and device buffer (grown if needed), one asynchronous copy on
+// st; the caller keeps ext alive and unused by other work until the batch's
+// launches have run.
+int upload_batch(BatchPlan* bp, BatchBuffers* ext, hipStream_t st) {
+    if (!ext) {
+        for (auto& g : bp->groups) {
+            if (g.image.empty()) continue;
+            if (hipMalloc(&g.dev, g.image.size()) != hipSuccess) {
+                g.dev = nullptr;
+                return set_error(TVS_E_NOMEM, "hipMalloc of the batch work list failed");
+            }
+            g.owned = true;
+            TVS_HIP_TRY(hipMemcpy(g.dev, g.image.data(), g.image.size(), hipMemcpyHostToDevice));
+        }
+        return TVS_OK;
+    }
+    size_t total = 0;
+    std::vector<size_t> off;
+    for (auto& g : bp->groups) {
+        off.push_back(total);
+        total += (g.image.size() + 255) & ~(size_t)255;
+    }
+    if (total == 0) return TVS_OK;
+    if (ext->capacity < total) {
+        size_t cap = std::max(total, 2 * ext->capacity);
+        if (ext->dev) (void)hipFree(ext->dev);
+        if (ext->host) (void)hipHostFree(ext->host);
+        ext->dev = ext->host = nullptr;
+        ext->capacity = 0;
+        if (hipMalloc(&ext->dev, cap) != hipSuccess) {
+            ext->dev = nullptr;
+            return set_error(TVS_E_NOMEM, "hipMalloc of the batch work lists failed");
+        }
+        if (hipHostMalloc(&ext->host, cap, hipHostMallocDefault) != hipSuccess) {
+            ext->host = nullptr;
+            return set_error(TVS_E_NOMEM, "hipHostMalloc of the batch staging failed");
+        }
+        ext->capacity = cap;
+    }
+    for (size_t i = 0; i < bp->groups.size(); ++i) {
+        auto& g = bp->groups[i];
+        if (g.image.empty()) continue;
+        std::memcpy((char*)ext->host + off[i], g.image.data(), g.image.size());
+        g.dev = (char*)ext->dev + off[i];
+        g.owned = false;
+    }
+    TVS_HIP_TRY(hipMemcpyAsync(ext->dev, ext->host, total, hipMemcpyHostToDevice, st));
+    return TVS_OK;
 }
 
 // Host work and uploads for the whole batch (no stream work).
@@ -422,10 +474,18 @@ void graph_cache_drop(tvs_plan* p) {
 }
 
 int batch_run(int n, tvs_plan* const* plans, void* const* grids, const double* const* coeffs,
-              const int64_t* T, hipStream_t st, bool use_graph) {
+              const int64_t* T, hipStream_t st, bool use_graph, BatchBuffers* ext) {
+    if (ext) {  // asynchronous: work lists in the caller's buffers, nothing waited for
+        BatchPlan bp;
+        int rc = prepare_batch(n, plans, grids, coeffs, T, &bp);
+        if (rc == TVS_OK) rc = upload_batch(&bp, ext, st);
+        if (rc == TVS_OK) rc = launch_batch(bp, grids, coeffs, T, st, true);
+        return rc;
+    }
     if (!use_graph) {
         BatchPlan bp;
         int rc = prepare_batch(n, plans, grids, coeffs, T, &bp);
+        if (rc == TVS_OK) rc = upload_batch(&bp, nullptr, st);
         if (rc == TVS_OK) rc = launch_batch(bp, grids, coeffs, T, st, true);
         // the work lists must outlive the launches that read them
         if (hipStreamSynchronize(st) != hipSuccess && rc == TVS_OK)
@@ -448,6 +508,7 @@ int batch_run(int n, tvs_plan* const* plans, void* const* grids, const double* c
         }
         GraphEntry e;
         int rc = prepare_batch(n, plans, grids, coeffs, T, &e.bp);
+        if (rc == TVS_OK) rc = upload_batch(&e.bp, nullptr, st);
         if (rc) {
             free_batch(&e.bp);
             return rc;
@@ -504,7 +565,7 @@ extern "C" int stencil_batch_run(int n, tvs_plan* const* plans, void* const* gri
     }
     const char* env = std::getenv("TVS_BATCH_GRAPH");
     const bool use_graph = !(env && env[0] == '0');
-    int rc = batch_run(n, plans, grids, coeffs, T, (hipStream_t)stream, use_graph);
+    int rc = batch_run(n, plans, grids, coeffs, T, (hipStream_t)stream, use_graph, nullptr);
     if (rc) return rc;
     for (int i = 0; i < n; ++i)
         if (plans[i]->prob.dependence == TVS_GAUSS_SEIDEL && T[i] > 0) {
