@@ -37,6 +37,7 @@
 // so this changes no bit.  The result is bit-identical to the naive sweep.
 #pragma once
 
+#include <algorithm>
 #include <type_traits>
 
 #include "kernels.hpp"
@@ -55,9 +56,51 @@ struct ArgsNd {
                       // starts at (r * (k + 1) + l) * PSP
     int G, Gx, NT;    // lanes per level, lane groups per tile row, threads
     int Lv, Lin;
-    int ntx, nty;
+    int ntx, nty, nseg;
     int lanemap;
+    // interior tile ranges [lo, hi) per axis: tiles that touch no fixed
+    // border (all tiles under periodic boundaries)
+    int ix0, ix1, iy0, iy1, is0, is1;
 };
+
+// Dispatch order of a band's tiles.  Tiles that touch a fixed border run the
+// slower border path; dispatched first, they overlap the interior tiles
+// instead of trailing them.  The interior tiles follow, spread so that each
+// XCD takes a contiguous range of them (neighbouring tiles share halo data
+// in its L2).  Maps block index blk to the tile's lexicographic index
+// (stream segment, row, column); a bijection on [0, tiles).
+__host__ __device__ inline int tile_order(int blk, const ArgsNd& a) {
+    const int ntx = a.ntx, nty = a.nty;
+    const int nix = a.ix1 - a.ix0, niy = a.iy1 - a.iy0, nis = a.is1 - a.is0;
+    const int plane = ntx * nty;
+    const int ni = nix * niy * nis;
+    const int nb = plane * a.nseg - ni;
+    auto lex = [&](int bs, int by, int bx) { return (bs * nty + by) * ntx + bx; };
+    if (blk >= nb) {  // interior
+        const int t = xcd_block(blk - nb, ni);
+        const int r = t / nix;
+        return lex(a.is0 + r / niy, a.iy0 + r % niy, a.ix0 + t % nix);
+    }
+    int r = blk;
+    const int before = a.is0 * plane;  // whole planes before the interior segments
+    if (r < before) return r;
+    r -= before;
+    const int per = plane - nix * niy;  // border tiles of a plane of an interior segment
+    if (r < nis * per) {
+        const int bs = a.is0 + r / per;
+        int q = r % per;
+        if (q < a.iy0 * ntx) return lex(bs, q / ntx, q % ntx);  // rows before
+        q -= a.iy0 * ntx;
+        const int m = ntx - nix;  // border tiles of an interior row
+        if (q < niy * m) {
+            const int qq = q % m;
+            return lex(bs, a.iy0 + q / m, qq < a.ix0 ? qq : a.ix1 + (qq - a.ix0));
+        }
+        q -= niy * m;
+        return lex(bs, a.iy1 + q / ntx, q % ntx);  // rows after
+    }
+    return lex(a.is1, 0, 0) + (r - nis * per);  // whole planes after
+}
 
 // One tile of one band.  Threads tid >= a.NT take part in the barriers only.
 // Returns after a final LDS barrier, so the caller may reuse the LDS.
@@ -208,8 +251,13 @@ __device__ __forceinline__ void tstp_tile(const T* __restrict__ in, T* __restric
         const int p = q - 2 * j + 1;  // stream position of the level-(j-1) plane read now
         if (p >= 0 && p < a.Lin) {
             const T* src = plane(j - 1, par ^ 1) + row_off;
+            // Shared products (equal weights) in interior tiles only: a border
+            // tile multiplies every term by its weight -- with equal weights the
+            // same rounded product -- so that v keeps the raw values, which
+            // are also the fixed border values of the next step (prevc).
+            constexpr bool SHARE = UNI && !BT;
             // v[r][i]: plane row ly-1+r, tile column lx-1+i (multiplied by the
-            // common weight when UNI)
+            // common weight when SHARE)
             T v[R][C + 2];
 #pragma unroll
             for (int r = 0; r < R; ++r) {
@@ -222,12 +270,7 @@ __device__ __forceinline__ void tstp_tile(const T* __restrict__ in, T* __restric
                     v[r][i] = rs[pos];
                 }
             }
-            T centre[C];
-            if constexpr (BT) {
-#pragma unroll
-                for (int c = 0; c < C; ++c) centre[c] = v[MID][1 + c];
-            }
-            if (UNI) {
+            if constexpr (SHARE) {
 #pragma unroll
                 for (int r = 0; r < R; ++r)
 #pragma unroll
@@ -246,7 +289,7 @@ __device__ __forceinline__ void tstp_tile(const T* __restrict__ in, T* __restric
             // one canonical term: weight * value, or the shared product
             auto add = [&](T acc, auto qc, int c, bool first) -> T {
                 constexpr int q2 = decltype(qc)::value;
-                const T prod = UNI ? val(qc, c) : cf.c[q2] * val(qc, c);
+                const T prod = SHARE ? val(qc, c) : cf.c[q2] * val(qc, c);
                 return first ? prod : acc + prod;
             };
             const int gz_out = z_org + p - 1;
@@ -273,7 +316,7 @@ __device__ __forceinline__ void tstp_tile(const T* __restrict__ in, T* __restric
                     const int gxc = x_org + lx + c;
                     const bool fixed = z_border || y_border || gxc == 0 || gxc == a.nx - 1;
                     if (emit && fixed) dst[c * S] = prevc[c];
-                    prevc[c] = centre[c];
+                    prevc[c] = v[MID][1 + c];
                 }
             }
         }
@@ -309,7 +352,7 @@ template <typename T, int D, bool BOX, bool PER, int C, int NPT, bool UNI>
 __global__ __launch_bounds__(512) void tstp_nd(const T* __restrict__ in, T* __restrict__ out,
                                                ArgsNd a, Coeffs<T> cf) {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
-    tstp_tile<T, D, BOX, PER, C, NPT, UNI>(in, out, a, cf, xcd_block(blockIdx.x, gridDim.x),
+    tstp_tile<T, D, BOX, PER, C, NPT, UNI>(in, out, a, cf, tile_order(blockIdx.x, a),
                                            reinterpret_cast<T*>(smem_raw), threadIdx.x);
 }
 
@@ -348,8 +391,32 @@ inline ArgsNd make_args(const Problem& p, const BandGeom& g) {
     a.Lv = g.Lv;
     a.Lin = g.Lv + 2 * g.k;
     a.ntx = g.ntx;
+    a.nseg = g.nseg;
     a.nty = g.nty;
     a.lanemap = g.lanemap;
+    // interior ranges, by the same test the kernel applies (border_tile)
+    a.ix0 = a.iy0 = a.is0 = 0;
+    a.ix1 = a.ntx;
+    a.iy1 = a.nty;
+    a.is1 = a.nseg;
+    if (p.boundary != TVS_PERIODIC) {
+        auto range = [](int n_tiles, int valid, int k, int ext, int n, int* lo, int* hi) {
+            *lo = n_tiles;
+            *hi = 0;
+            for (int t = 0; t < n_tiles; ++t) {
+                const int org = t * valid - k;
+                if (org > 0 && org + ext - 1 < n - 1) {
+                    *lo = std::min(*lo, t);
+                    *hi = std::max(*hi, t + 1);
+                }
+            }
+        };
+        range(a.ntx, a.Wv, a.k, a.W, a.nx, &a.ix0, &a.ix1);
+        range(a.nseg, a.Lv, a.k, a.Lin, a.nz, &a.is0, &a.is1);
+        if (D == 3) range(a.nty, a.Hv, a.k, a.H, a.ny, &a.iy0, &a.iy1);
+        if (a.ix1 <= a.ix0 || a.iy1 <= a.iy0 || a.is1 <= a.is0)
+            a.ix0 = a.ix1 = a.iy0 = a.iy1 = a.is0 = a.is1 = 0;  // no interior tile
+    }
     return a;
 }
 
