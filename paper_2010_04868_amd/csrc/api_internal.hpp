@@ -2,8 +2,20 @@
 #pragma once
 
 #include <string>
+#include <vector>
 
 #include "kernels.hpp"
+
+// A Jacobi run as the graph replay cache identifies it.
+struct RunKey {
+    void* grid = nullptr;
+    int64_t T = -1;
+    std::vector<double> coeffs;
+};
+struct RunGraph {
+    RunKey key;
+    hipGraphExec_t exec = nullptr;
+};
 
 struct tvs_plan {
     tvs::Problem prob;
@@ -13,6 +25,9 @@ struct tvs_plan {
     void* gs_work = nullptr;  // Gauss-Seidel ticket, status word, progress counters
     size_t gs_work_bytes = 0;
     bool external_scratch = false;  // scratch/gs_work lent by the owner (server arena)
+    RunKey last_run;                   // the previous eager run (graph replay cache)
+    std::vector<RunGraph> run_graphs;  // captured repeated runs
+    hipStream_t capture_stream = nullptr;
     int* gs_status_host = nullptr;  // pinned copy of the status word
     hipEvent_t gs_status_event = nullptr;
 };
@@ -42,12 +57,26 @@ std::string problem_key(const Problem& p);
 // Graph cache of a plan (captured launch sequences).
 void graph_cache_drop(tvs_plan* p);
 
+// Replay of repeated Jacobi runs: launches a captured graph for a run seen
+// before (*done = true), or leaves it to the caller (*done = false).
+int run_graph(tvs_plan* p, void* grid, const double* coeffs, int64_t T, hipStream_t st,
+              bool* done);
+void run_graphs_drop(tvs_plan* p);
+
 // Device work-list buffer and its pinned host staging, kept by a caller that
 // issues many batches (the server), so that a batch allocates nothing.
+// Optionally also streams on which the Gauss-Seidel members of a batch run
+// concurrently (each member's sweeps are one dependency chain that leaves
+// most of the device idle), forked from and joined back to the batch stream.
 struct BatchBuffers {
     void* dev = nullptr;
     void* host = nullptr;
     size_t capacity = 0;
+    static constexpr int kAux = 4;
+    int naux = 0;  // streams in aux (0: Gauss-Seidel members run on the batch stream)
+    hipStream_t aux[kAux] = {};
+    hipEvent_t fork = nullptr;
+    hipEvent_t join[kAux] = {};
 };
 
 // Enqueue one batch (stencil_batch_run's work).  With ext the work lists go

@@ -412,20 +412,34 @@ int prepare_batch(int n, tvs_plan* const* plans, void* const* grids, const doubl
 
 // Enqueue a prepared batch on st: the Jacobi rounds, and (with_gs) the
 // Gauss-Seidel members, which run through their own persistent kernel and
-// are kept out of captured graphs.
+// are kept out of captured graphs.  With ext->naux > 0 the Gauss-Seidel
+// members are spread over ext's auxiliary streams, after everything already
+// on st, and st waits for all of them.
 int launch_batch(const BatchPlan& bp, void* const* grids, const double* const* coeffs,
-                 const int64_t* T, hipStream_t st, bool with_gs) {
+                 const int64_t* T, hipStream_t st, bool with_gs, const BatchBuffers* ext = nullptr) {
     for (const auto& g : bp.groups) {
         int rc = g.v.dtype == TVS_F64 ? launch_group<double>(g, st) : launch_group<float>(g, st);
         if (rc) return rc;
     }
-    if (!with_gs) return TVS_OK;
-    for (const auto& m : bp.gs) {
+    if (!with_gs || bp.gs.empty()) return TVS_OK;
+    const int naux = ext ? std::min<int>(ext->naux, (int)bp.gs.size()) : 0;
+    if (naux > 1) {
+        TVS_HIP_TRY(hipEventRecord(ext->fork, st));
+        for (int a = 0; a < naux; ++a) TVS_HIP_TRY(hipStreamWaitEvent(ext->aux[a], ext->fork, 0));
+    }
+    for (size_t i = 0; i < bp.gs.size(); ++i) {
+        const auto& m = bp.gs[i];
         CoeffBuf cb;
         fill_coeffs(m.first->prob, coeffs[m.second], &cb);
-        int rc = enqueue_gs(m.first, grids[m.second], cb, T[m.second], st);
+        hipStream_t s = naux > 1 ? ext->aux[i % naux] : st;
+        int rc = enqueue_gs(m.first, grids[m.second], cb, T[m.second], s);
         if (rc) return rc;
     }
+    if (naux > 1)
+        for (int a = 0; a < naux; ++a) {
+            TVS_HIP_TRY(hipEventRecord(ext->join[a], ext->aux[a]));
+            TVS_HIP_TRY(hipStreamWaitEvent(st, ext->join[a], 0));
+        }
     return TVS_OK;
 }
 
@@ -479,7 +493,7 @@ int batch_run(int n, tvs_plan* const* plans, void* const* grids, const double* c
         BatchPlan bp;
         int rc = prepare_batch(n, plans, grids, coeffs, T, &bp);
         if (rc == TVS_OK) rc = upload_batch(&bp, ext, st);
-        if (rc == TVS_OK) rc = launch_batch(bp, grids, coeffs, T, st, true);
+        if (rc == TVS_OK) rc = launch_batch(bp, grids, coeffs, T, st, true, ext);
         return rc;
     }
     if (!use_graph) {

@@ -7,6 +7,8 @@
 // measured against, so it is written to stream well: the stream axis is
 // walked by each thread with a register window, the inner axes are
 // coalesced and their neighbour re-reads hit in L1/L2.
+#include <algorithm>
+
 #include "kernels.hpp"
 
 namespace tvs {
@@ -147,6 +149,27 @@ hipError_t plain_step_t(const Problem& p, const T* in, T* out, const Coeffs<T>& 
 }
 
 }  // namespace
+
+// Device-to-device copy as a kernel (16-byte words, then the tail): unlike a
+// runtime copy it records a plain kernel node when a run is captured in a
+// graph.
+__global__ void copy_words(const uint4* __restrict__ src, uint4* __restrict__ dst, int64_t nw,
+                           const unsigned char* __restrict__ src_tail,
+                           unsigned char* __restrict__ dst_tail, int tail) {
+    const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (int64_t i = i0; i < nw; i += (int64_t)gridDim.x * blockDim.x) dst[i] = src[i];
+    if (i0 < tail) dst_tail[i0] = src_tail[i0];
+}
+
+hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t st) {
+    const int64_t nw = (int64_t)(bytes / 16);
+    const int tail = (int)(bytes % 16);
+    const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>(8192, (nw + 255) / 256));
+    hipLaunchKernelGGL(copy_words, dim3((unsigned)blocks), dim3(256), 0, st, (const uint4*)src,
+                       (uint4*)dst, nw, (const unsigned char*)src + nw * 16,
+                       (unsigned char*)dst + nw * 16, tail);
+    return hipGetLastError();
+}
 
 hipError_t launch_plain_step(const Problem& p, const void* in, void* out, const void* coeffs,
                              hipStream_t st) {

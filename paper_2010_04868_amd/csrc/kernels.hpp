@@ -9,6 +9,9 @@ namespace tvs {
 hipError_t launch_plain_step(const Problem& p, const void* in, void* out, const void* coeffs,
                              hipStream_t st);
 
+// Copy bytes device to device with a kernel (graph-capture friendly).
+hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t st);
+
 // Geometry of one time-skewed band: derived from the schedule for a band of
 // `k` levels.  Shared by the launcher, the batch kernel and the tuner.
 struct BandGeom {

@@ -324,8 +324,14 @@ void destroy_chunks(tvs_server* s) {
     for (auto& c : s->chunks) {
         if (c.start) (void)hipEventDestroy(c.start);
         if (c.end) (void)hipEventDestroy(c.end);
-        if (c.buffers.dev) (void)hipFree(c.buffers.dev);
-        if (c.buffers.host) (void)hipHostFree(c.buffers.host);
+        BatchBuffers& b = c.buffers;
+        if (b.dev) (void)hipFree(b.dev);
+        if (b.host) (void)hipHostFree(b.host);
+        if (b.fork) (void)hipEventDestroy(b.fork);
+        for (int a = 0; a < BatchBuffers::kAux; ++a) {
+            if (b.aux[a]) (void)hipStreamDestroy(b.aux[a]);
+            if (b.join[a]) (void)hipEventDestroy(b.join[a]);
+        }
         c = Chunk();
     }
 }
@@ -357,10 +363,23 @@ int stencil_server_create(tvs_server** out, size_t hbm_budget, int max_slots, in
             s->stream = nullptr;
             rc = set_error(TVS_E_DEVICE, "stream creation failed");
         }
-        for (auto& c : s->chunks)
+        for (auto& c : s->chunks) {
             if (!rc && (hipEventCreate(&c.start) != hipSuccess ||
                         hipEventCreate(&c.end) != hipSuccess))
                 rc = set_error(TVS_E_DEVICE, "event creation failed");
+            // Gauss-Seidel requests of a chunk run side by side on these
+            // (default-priority) streams
+            BatchBuffers& b = c.buffers;
+            if (!rc && hipEventCreateWithFlags(&b.fork, hipEventDisableTiming) != hipSuccess)
+                rc = set_error(TVS_E_DEVICE, "event creation failed");
+            for (int a = 0; a < BatchBuffers::kAux && !rc; ++a) {
+                if (hipStreamCreateWithFlags(&b.aux[a], hipStreamNonBlocking) != hipSuccess ||
+                    hipEventCreateWithFlags(&b.join[a], hipEventDisableTiming) != hipSuccess)
+                    rc = set_error(TVS_E_DEVICE, "stream creation failed");
+                else
+                    b.naux = a + 1;
+            }
+        }
         if (rc) {
             destroy_chunks(s);
             if (s->stream) (void)hipStreamDestroy(s->stream);

@@ -102,9 +102,10 @@ __host__ __device__ inline int tile_order(int blk, const ArgsNd& a) {
     return lex(a.is1, 0, 0) + (r - nis * per);  // whole planes after
 }
 
-// One tile of one band.  Threads tid >= a.NT take part in the barriers only.
-// Returns after a final LDS barrier, so the caller may reuse the LDS.
-template <typename T, int D, bool BOX, bool PER, int C, int NPT, bool UNI>
+// One tile of one band.  Threads tid >= a.NT take part in the barriers only
+// (AW: the block has exactly a.NT threads).  Returns after a final LDS
+// barrier, so the caller may reuse the LDS.
+template <typename T, int D, bool BOX, bool PER, int C, int NPT, bool UNI, bool AW = false>
 __device__ __forceinline__ void tstp_tile(const T* __restrict__ in, T* __restrict__ out,
                                           const ArgsNd& a, const Coeffs<T>& cf, int tile, T* lds,
                                           int tid) {
@@ -116,7 +117,7 @@ __device__ __forceinline__ void tstp_tile(const T* __restrict__ in, T* __restric
     constexpr int R = D == 3 ? 3 : 1;  // plane rows a lane reads
     constexpr int MID = D == 3 ? 1 : 0;
 
-    const bool worker = tid < a.NT;
+    const bool worker = AW || tid < a.NT;
     const int k = a.k;
     const int S = a.S;
     const int Wp = a.Wp;
@@ -137,8 +138,8 @@ __device__ __forceinline__ void tstp_tile(const T* __restrict__ in, T* __restric
         j = 1 + tid / a.G;
         g = tid % a.G;
     }
-    if (!worker) {  // idle thread: keep it out of every level's range
-        j = 1 << 20;
+    if (!worker) {  // idle thread: valid addresses, no stores
+        j = 1;
         g = 0;
     }
     const int ly = D == 3 ? g / a.Gx : 0;  // lane's tile row (3D)
@@ -190,12 +191,24 @@ __device__ __forceinline__ void tstp_tile(const T* __restrict__ in, T* __restric
             if (valid) st_off[i] = (uint32_t)(oy * a.nx + ox) * (uint32_t)sizeof(T);
         }
     }
-    const int64_t plane_elems = (int64_t)a.ny * a.nx;
-    const uint32_t plane_bytes = (uint32_t)(plane_elems * (int64_t)sizeof(T));
+    // Row addresses in 32-bit scalar arithmetic: a plane is below 2 GiB, so
+    // row * plane_bytes is one 32 x 32 -> 64-bit product.
+    const uint32_t plane_bytes = (uint32_t)a.ny * (uint32_t)a.nx * (uint32_t)sizeof(T);
+    auto row_ptr = [&](const T* base, int row) {
+        return (const T*)((const char*)base + (uint64_t)(uint32_t)row * plane_bytes);
+    };
+    // periodic: the row of the next load, wrapped incrementally (loads are
+    // issued for q = 0, 1, 2, ... in order)
+    int ld_row = PER ? (int)wrap_idx(z_org, a.nz) : 0;
     auto issue_load = [&](int q, T* dst) {
-        int64_t gz = z_org + q;
-        gz = PER ? wrap_idx(gz, a.nz) : clamp_idx(gz, a.nz);
-        const auto rs = buf_rsrc(in + gz * plane_elems, q < a.Lin ? plane_bytes : 0u);
+        int gz;
+        if (PER) {
+            gz = ld_row;
+            ld_row = ld_row + 1 == a.nz ? 0 : ld_row + 1;
+        } else {
+            gz = min(max(z_org + q, 0), a.nz - 1);
+        }
+        const auto rs = buf_rsrc(row_ptr(in, gz), q < a.Lin ? plane_bytes : 0u);
 #pragma unroll
         for (int i = 0; i < NPT; ++i) dst[i] = buf_load<T>(rs, ld_off[i]);
     };
@@ -210,25 +223,27 @@ __device__ __forceinline__ void tstp_tile(const T* __restrict__ in, T* __restric
     // level k emitted tile row q-1-2k at step q-1 into its plane; write it out
     auto store_output = [&](int q, int par) {
         const int row = q - 1 - 2 * k;
-        const int64_t gz = (int64_t)z_org + row;
+        const int gz = z_org + row;
         const bool ok = row >= k && row < a.Lin - k && gz < a.nz;
         const T* pl = plane(k, par ^ 1);
-        const auto rs = buf_rsrc(out + (ok ? gz : 0) * plane_elems, ok ? plane_bytes : 0u);
+        const auto rs = buf_rsrc(row_ptr(out, ok ? gz : 0), ok ? plane_bytes : 0u);
 #pragma unroll
         for (int i = 0; i < NPT; ++i) buf_store<T>(rs, st_off[i], pl[st_lds[i] < 0 ? 0 : st_lds[i]]);
     };
 
-    // running sums of a lane's points: Macc lacks the terms of the stencil
-    // row ahead (it becomes this step's output), Sacc lacks the centre and
-    // ahead rows
-    T Sacc[C], Macc[C];
+    // Running sums of a lane's points, two per point.  At a step of parity r,
+    // Acc[r] lacks only the terms of the stencil row ahead (it becomes this
+    // step's output) and Acc[r^1] lacks the centre and ahead rows (it gains
+    // the centre row in place); Acc[r] then starts the sums of the new row.
+    // The roles swap with the parity, so no value is copied.
+    T Acc[2][C];
     // Dirichlet: a fixed border point has the same value at every level, so
     // its level-j value is level j-1's value at the same point -- the centre
     // value this lane read one step earlier (stream row p-1).  Keeping those
     // raw values avoids a global load (and its wait) in the step.
     T prevc[C];
 #pragma unroll
-    for (int c = 0; c < C; ++c) Sacc[c] = Macc[c] = prevc[c] = T(0);
+    for (int c = 0; c < C; ++c) Acc[0][c] = Acc[1][c] = prevc[c] = T(0);
     const T cu = cf.c[0];  // the common weight when UNI
 
     const int row_off = D == 3 ? ly * Wp : 0;  // padded row ly holds tile row ly-1
@@ -249,7 +264,14 @@ __device__ __forceinline__ void tstp_tile(const T* __restrict__ in, T* __restric
         issue_load(q + DP, pr);
         store_output(q, par);
         const int p = q - 2 * j + 1;  // stream position of the level-(j-1) plane read now
-        if (p >= 0 && p < a.Lin) {
+        // Interior tiles compute at every step, also outside the level's
+        // stream range [0, Lin): such steps read rows not (or no longer)
+        // produced and store garbage rows, but a valid output row r of a level
+        // reads only rows r-1..r+1 of the level below, which are valid, and
+        // its running sum is assigned afresh two steps before it is stored;
+        // garbage only ever reaches rows outside the trapezoid, which are
+        // never stored to HBM.  This keeps divergent branches out of the step.
+        if (!BT || (p >= 0 && p < a.Lin)) {
             const T* src = plane(j - 1, par ^ 1) + row_off;
             // Shared products (equal weights) in interior tiles only: a border
             // tile multiplies every term by its weight -- with equal weights the
@@ -294,20 +316,20 @@ __device__ __forceinline__ void tstp_tile(const T* __restrict__ in, T* __restric
             };
             const int gz_out = z_org + p - 1;
             const bool z_border = !PER && (gz_out == 0 || gz_out == a.nz - 1);
-            const bool emit = p >= 1;
+            const bool emit = worker && (!BT || p >= 1);
             T* dst = plane(j, par) + (D == 3 ? row_off + Wp : 0) + gx + 1;
 #pragma unroll
             for (int c = 0; c < C; ++c) {
-                T f = Macc[c];
+                T f = Acc[par][c];
                 static_for<gp_b, gp_e>([&](auto qc) { f = add(f, qc, c, false); });
-                T m = Sacc[c];
+                T m = Acc[par ^ 1][c];
                 static_for<g0_b, g0_e>([&](auto qc) { m = add(m, qc, c, false); });
                 T s = T(0);
                 static_for<gm_b, gm_e>([&](auto qc) {
                     s = add(s, qc, c, decltype(qc)::value == gm_b);
                 });
-                Macc[c] = m;
-                Sacc[c] = s;
+                Acc[par ^ 1][c] = m;
+                Acc[par][c] = s;
                 if (emit) dst[c * S] = f;
                 if constexpr (BT) {
                     // a fixed border point keeps its input value at every level:
@@ -352,7 +374,7 @@ template <typename T, int D, bool BOX, bool PER, int C, int NPT, bool UNI>
 __global__ __launch_bounds__(512) void tstp_nd(const T* __restrict__ in, T* __restrict__ out,
                                                ArgsNd a, Coeffs<T> cf) {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
-    tstp_tile<T, D, BOX, PER, C, NPT, UNI>(in, out, a, cf, tile_order(blockIdx.x, a),
+    tstp_tile<T, D, BOX, PER, C, NPT, UNI, true>(in, out, a, cf, tile_order(blockIdx.x, a),
                                            reinterpret_cast<T*>(smem_raw), threadIdx.x);
 }
 

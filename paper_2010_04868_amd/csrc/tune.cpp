@@ -267,6 +267,7 @@ extern "C" int stencil_tune(tvs_plan* p, void* grid, const double* coeffs, int64
     }
     p->sched = best_s;
     graph_cache_drop(p);
+    run_graphs_drop(p);
     tune_cache_store(pr, best_s);
     if (best && best_len) {
         std::string t = format_tuning(pr, best_s);

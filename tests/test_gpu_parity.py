@@ -121,3 +121,33 @@ def test_composition_bitwise(dep):
     assert_bitwise(whole, part, "composition")
     ref = oracle_sweep(u0, c, STAR, 5, dep, DIRICHLET, 23)
     assert_bitwise(whole, ref, "vs oracle")
+
+
+@pytest.mark.parametrize("dims,shape,order,tuning,T", [
+    ((130, 301), BOX, 9, None, 70),                        # 9 launches: copy back
+    ((5000,), STAR, 3, "method=tstp,k=16,l=64,pl=16", 200),  # 1D, 13 bands
+    ((33, 40, 47), STAR, 7, None, 33),                     # 3D, 9 launches: copy back
+    ((64, 70), STAR, 5, "method=plain", 12),               # plain steps, even count
+])
+@pytest.mark.parametrize("graph", ["0", "1"])
+def test_repeated_runs_replay(dims, shape, order, tuning, T, graph, monkeypatch):
+    """The same run requested again is replayed from a captured graph; every
+    replay must equal the oracle at T * (replay count), with unrelated eager
+    device work between the replays."""
+    import torch
+
+    import paper_2010_04868_amd as tvs
+    monkeypatch.setenv("TVS_RUN_GRAPH", graph)
+    u0 = np.random.default_rng(11).random(dims)
+    c = _coeffs(order, 5)
+    plan = tvs.Plan(dims, F64, shape, order, JACOBI, DIRICHLET, tuning)
+    g = torch.from_numpy(u0).to("cuda")
+    want = u0
+    for rep in range(1, 5):
+        plan.run(g, c, T)
+        torch.cuda.synchronize()
+        noise = torch.ones(4096, device="cuda", dtype=torch.float64).cumsum(0)
+        torch.cuda.synchronize()
+        want = oracle_sweep(want, c, shape, order, JACOBI, DIRICHLET, T)
+        assert_bitwise(g.cpu().numpy(), want, f"{dims} replay {rep} graph={graph}")
+        del noise
