@@ -113,7 +113,8 @@ int enqueue_gs(tvs_plan* p, void* grid, const CoeffBuf& cb, int64_t T, hipStream
     int64_t done = 0;
     while (done < T) {
         const int sw = (int)std::min<int64_t>(per_launch, T - done);
-        TVS_HIP_TRY(launch_gs(p->prob, grid, cb.bytes, sw, p->gs_work, st));
+        const int hr = p->sched.method == TVS_METHOD_PLAIN ? 1 : p->sched.c;
+        TVS_HIP_TRY(launch_gs(p->prob, grid, cb.bytes, sw, hr, p->gs_work, st));
         done += sw;
     }
     return TVS_OK;

@@ -95,9 +95,28 @@ __device__ void decode_item(int item, int nb, int sweeps, int* b, int* t) {
     }
 }
 
-template <typename T, bool BOX>
+// Value of lane 63 in every lane (wave-wide readlane).
+template <typename T>
+__device__ __forceinline__ T lane63(T v) {
+    if constexpr (sizeof(T) == 8) {
+        const long long b = __double_as_longlong(v);
+        const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), 63);
+        const int hi = __builtin_amdgcn_readlane((int)(b >> 32), 63);
+        return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+    } else {
+        return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
+    }
+}
+
+// HR rows per lane: lane i owns rows x0+i, x0+64+i, ... of a band of 64*HR
+// rows.  The halves form one wavefront (half h runs 64*SIG columns behind
+// half h-1), so each lane carries HR independent dependency chains; the row
+// above the first row of half h is the last row of half h-1, whose value
+// comes from lane 63 by a readlane.
+template <typename T, bool BOX, int HR>
 __global__ __launch_bounds__(64) void gs2d(T* grid, GsArgs a, Coeffs<T> cf) {
     constexpr int SIG = BOX ? 2 : 1;
+    constexpr int BR = kRows * HR;  // rows per band
     const int lane = threadIdx.x;
     const int64_t n1 = a.n1;
     for (;;) {
@@ -107,14 +126,26 @@ __global__ __launch_bounds__(64) void gs2d(T* grid, GsArgs a, Coeffs<T> cf) {
         if (item >= a.nitems) break;
         int b, t;
         decode_item(item, a.nb, a.sweeps, &b, &t);
-        const int x0 = 1 + kRows * b;
-        const int rows = min(kRows, a.n0 - 1 - x0);
-        const int L = rows - 1;  // last active lane
-        const int x = x0 + lane;
-        const bool active = lane < rows;
-        const int xr = active ? x : x0;  // safe row for inactive lanes
-        T* row = grid + (int64_t)xr * n1;
-        const T* row_s = grid + (int64_t)(xr + 1) * n1;
+        const int x0 = 1 + BR * b;
+        const int rows = min(BR, a.n0 - 1 - x0);
+        const int L = rows - 1;  // last active row of the band
+        bool active[HR];
+        T* row[HR];
+        const T* row_s[HR];
+        // registers per half: west (new), centre/east (old), north and south histories
+        T Wv[HR], Cv[HR], Ev[HR], NWv[HR], Nv[HR], NEv[HR], SWv[HR], Sv[HR], SEv[HR], out[HR];
+#pragma unroll
+        for (int h = 0; h < HR; ++h) {
+            const int ri = kRows * h + lane;
+            active[h] = ri < rows;
+            const int xr = x0 + (active[h] ? ri : 0);  // safe row for inactive lanes
+            row[h] = grid + (int64_t)xr * n1;
+            row_s[h] = grid + (int64_t)(xr + 1) * n1;
+            Wv[h] = Cv[h] = out[h] = 0;
+            Ev[h] = row[h][0];
+            NWv[h] = Nv[h] = NEv[h] = grid[(int64_t)(xr - 1) * n1];
+            SWv[h] = Sv[h] = SEv[h] = row_s[h][0];
+        }
         const T* row_n = grid + (int64_t)(x0 - 1) * n1;  // lane 0's north row
         int* prog_self = a.progress + t * a.nb + b;
         const int* prog_north = b > 0 ? a.progress + t * a.nb + (b - 1) : nullptr;
@@ -122,14 +153,10 @@ __global__ __launch_bounds__(64) void gs2d(T* grid, GsArgs a, Coeffs<T> cf) {
         const int* prog_south =
             (t > 0 && b + 1 < a.nb) ? a.progress + (t - 1) * a.nb + (b + 1) : nullptr;
 
-        // registers: west (new), centre/east (old), north and south histories
-        T Wv = 0, Cv = 0, Ev = row[0];
-        T NWv = grid[(int64_t)(xr - 1) * n1], Nv = NWv, NEv = NWv;
-        T SWv = row_s[0], Sv = SWv, SEv = SWv;
-        T out = 0;
-        const int U = a.ncols + 2 + SIG * L;  // steps: column c = u - 1 - SIG*lane in [-1, ncols]
+        // steps: row ri of the band is at column c = u - 1 - SIG*ri in [-1, ncols]
+        const int U = a.ncols + 2 + SIG * L;
         for (int us = 0; us < U; us += kSync) {
-          // columns the leading lane (lane 0) reaches in this interval
+          // columns the leading row (lane 0 of the first half) reaches in this interval
           const int cmax = us + kSync - 2;
           if (prog_prev) wait_at_least(prog_prev, min(a.ncols, cmax + 2), a.status);
           if (prog_south) wait_at_least(prog_south, min(a.ncols, cmax + 2), a.status);
@@ -137,63 +164,76 @@ __global__ __launch_bounds__(64) void gs2d(T* grid, GsArgs a, Coeffs<T> cf) {
           // the producers' rows written before their progress stores are visible now
           __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
           for (int u0 = us; u0 < us + kSync && u0 < U; u0 += kBlock) {
-            T e_in[kBlock], se_in[kBlock], n_in[kBlock];
+            T e_in[HR][kBlock], se_in[HR][kBlock], n_in[kBlock];
 #pragma unroll
             for (int m = 0; m < kBlock; ++m) {
-                const int c = u0 + m - 1 - SIG * lane;
-                const int ye = c + 2;
-                e_in[m] = se_in[m] = n_in[m] = 0;
-                if (active && c >= -1 && ye <= a.n1 - 1) {
-                    e_in[m] = row[ye];
-                    se_in[m] = row_s[ye];
+#pragma unroll
+                for (int h = 0; h < HR; ++h) {
+                    const int c = u0 + m - 1 - SIG * (kRows * h + lane);
+                    const int ye = c + 2;
+                    e_in[h][m] = se_in[h][m] = 0;
+                    if (active[h] && c >= -1 && ye <= a.n1 - 1) {
+                        e_in[h][m] = row[h][ye];
+                        se_in[h][m] = row_s[h][ye];
+                    }
                 }
-                const int yn = c + SIG;
-                if (lane == 0 && c >= -1 && yn <= a.n1 - 1) n_in[m] = row_n[yn];
+                const int c0 = u0 + m - 1 - SIG * lane;
+                const int yn = c0 + SIG;
+                n_in[m] = 0;
+                if (lane == 0 && c0 >= -1 && yn <= a.n1 - 1) n_in[m] = row_n[yn];
             }
 #pragma unroll
             for (int m = 0; m < kBlock; ++m) {
-                const int c = u0 + m - 1 - SIG * lane;
-                // value of the row above, one column ahead of where the lane
-                // above was last step: lane i-1's last output, or memory for lane 0
-                const T nin = shift_up<64>(out, n_in[m]);
-                if (c >= -1 && c <= a.ncols) {
-                    if (BOX) {
-                        NWv = Nv;
-                        Nv = NEv;
-                        NEv = nin;
-                        SWv = Sv;
-                        Sv = SEv;
-                        SEv = se_in[m];
-                    } else {
-                        Nv = nin;
-                        Sv = SEv;
-                        SEv = se_in[m];
-                    }
-                    Cv = Ev;
-                    Ev = e_in[m];
-                    T r = Cv;  // border columns pass their fixed value along
-                    if (c >= 0 && c < a.ncols) {
+                // value of the row above, one column ahead of where the row
+                // above was last step: lane i-1's last output; for lane 0 the
+                // north row in memory (first half) or lane 63's last output of
+                // the half before (taken before this step updates it)
+                T nin[HR];
+                nin[0] = shift_up<64>(out[0], n_in[m]);
+#pragma unroll
+                for (int h = 1; h < HR; ++h) nin[h] = shift_up<64>(out[h], lane63(out[h - 1]));
+#pragma unroll
+                for (int h = 0; h < HR; ++h) {
+                    const int c = u0 + m - 1 - SIG * (kRows * h + lane);
+                    if (c >= -1 && c <= a.ncols) {
                         if (BOX) {
-                            r = cf.c[0] * NWv;
-                            r = r + cf.c[1] * Nv;
-                            r = r + cf.c[2] * NEv;
-                            r = r + cf.c[3] * Wv;
-                            r = r + cf.c[4] * Cv;
-                            r = r + cf.c[5] * Ev;
-                            r = r + cf.c[6] * SWv;
-                            r = r + cf.c[7] * Sv;
-                            r = r + cf.c[8] * SEv;
+                            NWv[h] = Nv[h];
+                            Nv[h] = NEv[h];
+                            NEv[h] = nin[h];
+                            SWv[h] = Sv[h];
+                            Sv[h] = SEv[h];
+                            SEv[h] = se_in[h][m];
                         } else {
-                            r = cf.c[0] * Nv;
-                            r = r + cf.c[1] * Wv;
-                            r = r + cf.c[2] * Cv;
-                            r = r + cf.c[3] * Ev;
-                            r = r + cf.c[4] * Sv;
+                            Nv[h] = nin[h];
+                            Sv[h] = SEv[h];
+                            SEv[h] = se_in[h][m];
                         }
-                        if (active) row[c + 1] = r;
+                        Cv[h] = Ev[h];
+                        Ev[h] = e_in[h][m];
+                        T r = Cv[h];  // border columns pass their fixed value along
+                        if (c >= 0 && c < a.ncols) {
+                            if (BOX) {
+                                r = cf.c[0] * NWv[h];
+                                r = r + cf.c[1] * Nv[h];
+                                r = r + cf.c[2] * NEv[h];
+                                r = r + cf.c[3] * Wv[h];
+                                r = r + cf.c[4] * Cv[h];
+                                r = r + cf.c[5] * Ev[h];
+                                r = r + cf.c[6] * SWv[h];
+                                r = r + cf.c[7] * Sv[h];
+                                r = r + cf.c[8] * SEv[h];
+                            } else {
+                                r = cf.c[0] * Nv[h];
+                                r = r + cf.c[1] * Wv[h];
+                                r = r + cf.c[2] * Cv[h];
+                                r = r + cf.c[3] * Ev[h];
+                                r = r + cf.c[4] * Sv[h];
+                            }
+                            if (active[h]) row[h][c + 1] = r;
+                        }
+                        Wv[h] = r;
+                        out[h] = r;
                     }
-                    Wv = r;
-                    out = r;
                 }
             }
           }
@@ -208,13 +248,14 @@ __global__ __launch_bounds__(64) void gs2d(T* grid, GsArgs a, Coeffs<T> cf) {
 }
 
 template <typename T>
-hipError_t launch_gs_t(const Problem& p, T* grid, const Coeffs<T>& cf, int sweeps, void* work,
-                       hipStream_t st) {
+hipError_t launch_gs_t(const Problem& p, T* grid, const Coeffs<T>& cf, int sweeps, int hr,
+                       void* work, hipStream_t st) {
+    if (hr != 1 && hr != 2) return hipErrorInvalidValue;
     GsArgs a{};
     a.n0 = (int)p.dims[0];
     a.n1 = (int)p.dims[1];
     a.ncols = a.n1 - 2;
-    a.nb = (a.n0 - 2 + kRows - 1) / kRows;
+    a.nb = (a.n0 - 2 + kRows * hr - 1) / (kRows * hr);
     a.sweeps = sweeps;
     a.nitems = a.nb * sweeps;
     int* w = (int*)work;
@@ -225,10 +266,13 @@ hipError_t launch_gs_t(const Problem& p, T* grid, const Coeffs<T>& cf, int sweep
     hipLaunchKernelGGL(gs_reset, dim3((unsigned)std::min(1024, (nprog + 255) / 256 + 1)),
                        dim3(256), 0, st, a.ticket, a.progress, nprog);
     const int waves = std::min(a.nitems, 256 * 8);
-    if (p.shape == TVS_BOX)
-        hipLaunchKernelGGL((gs2d<T, true>), dim3(waves), dim3(64), 0, st, grid, a, cf);
-    else
-        hipLaunchKernelGGL((gs2d<T, false>), dim3(waves), dim3(64), 0, st, grid, a, cf);
+    if (p.shape == TVS_BOX) {
+        if (hr == 2) hipLaunchKernelGGL((gs2d<T, true, 2>), dim3(waves), dim3(64), 0, st, grid, a, cf);
+        else hipLaunchKernelGGL((gs2d<T, true, 1>), dim3(waves), dim3(64), 0, st, grid, a, cf);
+    } else {
+        if (hr == 2) hipLaunchKernelGGL((gs2d<T, false, 2>), dim3(waves), dim3(64), 0, st, grid, a, cf);
+        else hipLaunchKernelGGL((gs2d<T, false, 1>), dim3(waves), dim3(64), 0, st, grid, a, cf);
+    }
     return hipGetLastError();
 }
 
@@ -239,12 +283,13 @@ size_t gs_work_bytes(const Problem& p, int sweeps) {
     return (size_t)(64 + nb * sweeps + 64) * sizeof(int);
 }
 
-hipError_t launch_gs(const Problem& p, void* grid, const void* coeffs, int sweeps, void* work,
-                     hipStream_t st) {
+hipError_t launch_gs(const Problem& p, void* grid, const void* coeffs, int sweeps, int hr,
+                     void* work, hipStream_t st) {
     if (p.dtype == TVS_F64)
-        return launch_gs_t<double>(p, (double*)grid, *(const Coeffs<double>*)coeffs, sweeps, work,
-                                   st);
-    return launch_gs_t<float>(p, (float*)grid, *(const Coeffs<float>*)coeffs, sweeps, work, st);
+        return launch_gs_t<double>(p, (double*)grid, *(const Coeffs<double>*)coeffs, sweeps, hr,
+                                   work, st);
+    return launch_gs_t<float>(p, (float*)grid, *(const Coeffs<float>*)coeffs, sweeps, hr, work,
+                              st);
 }
 
 hipError_t gs_read_status(const void* work, int* status, hipStream_t st) {

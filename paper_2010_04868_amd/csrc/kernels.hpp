@@ -40,11 +40,12 @@ bool band_geometry(const Problem& p, const Schedule& s, int k, BandGeom* g);
 hipError_t launch_tstp_band(const Problem& p, const BandGeom& g, const void* in, void* out,
                             const void* coeffs, hipStream_t st);
 
-// Gauss-Seidel: `sweeps` in-place sweeps of grid in one persistent launch.
-// `work` is device scratch of gs_work_bytes(p, sweeps) bytes.
+// Gauss-Seidel: `sweeps` in-place sweeps of grid in one persistent launch,
+// `hr` (1 or 2) rows per lane.  `work` is device scratch of
+// gs_work_bytes(p, sweeps) bytes (enough for either hr).
 size_t gs_work_bytes(const Problem& p, int sweeps);
-hipError_t launch_gs(const Problem& p, void* grid, const void* coeffs, int sweeps, void* work,
-                     hipStream_t st);
+hipError_t launch_gs(const Problem& p, void* grid, const void* coeffs, int sweeps, int hr,
+                     void* work, hipStream_t st);
 // Status word written by the Gauss-Seidel kernel (0 = ok) lives in `work`.
 hipError_t gs_read_status(const void* work, int* status, hipStream_t st);
 

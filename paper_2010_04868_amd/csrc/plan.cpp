@@ -125,7 +125,7 @@ std::string format_tuning(const Problem& p, const Schedule& s) {
     char buf[160];
     if (s.method == TVS_METHOD_PLAIN) return "method=plain";
     if (p.dependence == TVS_GAUSS_SEIDEL) {
-        std::snprintf(buf, sizeof buf, "method=tstp,k=%d", s.k);
+        std::snprintf(buf, sizeof buf, "method=tstp,k=%d,c=%d", s.k, s.c);
     } else if (p.ndim == 1) {
         std::snprintf(buf, sizeof buf, "method=tstp,k=%d,l=%d,pl=%d", s.k, s.l, s.pl);
     } else {
@@ -183,8 +183,11 @@ Schedule default_schedule(const Problem& p) {
     s.method = TVS_METHOD_TSTP;
     if (p.dependence == TVS_GAUSS_SEIDEL) {
         // sweeps per launch: more sweeps in flight hide the dependency waits
-        // (measured best 32..64 on 600^2 to 4096^2 grids)
+        // (measured best 32..64 on 600^2 to 4096^2 grids).  One row per
+        // lane: two rows per lane halve the number of bands in flight and
+        // measured slower on both sizes (a tuner candidate only).
         s.k = 32;
+        s.c = 1;
         return s;
     }
     const bool f64 = p.dtype == TVS_F64;
@@ -247,6 +250,8 @@ int check_schedule(const Problem& p, const Schedule& s) {
     if (s.k < 1) return set_error(TVS_E_INVALID, "k must be >= 1");
     if (p.dependence == TVS_GAUSS_SEIDEL) {
         if (s.k > 256) return set_error(TVS_E_INVALID, "k must be <= 256 for Gauss-Seidel");
+        if (s.c != 1 && s.c != 2)
+            return set_error(TVS_E_INVALID, "c (rows per lane) must be 1 or 2 for Gauss-Seidel");
         return TVS_OK;
     }
     if (s.s != 2)

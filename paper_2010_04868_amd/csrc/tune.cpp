@@ -89,11 +89,13 @@ std::vector<Schedule> tune_candidates(const Problem& p) {
     plain.method = TVS_METHOD_PLAIN;
     add(plain);
     if (p.dependence == TVS_GAUSS_SEIDEL) {
-        for (int k : {1, 2, 4, 16, 32}) {
-            Schedule s = base;
-            s.k = k;
-            add(s);
-        }
+        for (int c : {1, 2})
+            for (int k : {4, 8, 16, 32, 64}) {
+                Schedule s = base;
+                s.k = k;
+                s.c = c;
+                add(s);
+            }
         return out;
     }
     if (p.ndim == 1) {
@@ -108,7 +110,7 @@ std::vector<Schedule> tune_candidates(const Problem& p) {
                     add(s);
                 }
     } else if (p.ndim == 2) {
-        for (int c : {4, 8})
+        for (int c : {4, 8, 16})
             for (int k : {4, 6, 8, 12, 16})
                 for (int w : {128, 256, 512})
                     for (int lm : {0, 1}) {

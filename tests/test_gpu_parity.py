@@ -72,7 +72,8 @@ def test_gauss_seidel_matches_oracle(shape, dtype):
         u0 = np.random.default_rng(sum(dims)).random(dims).astype(np_dtype(dtype))
         for T in (1, 2, 5, 9):
             ref = oracle_sweep(u0, coeffs, shape, P, GAUSS_SEIDEL, DIRICHLET, T)
-            for tuning in ("method=plain", "method=tstp,k=1", "method=tstp,k=3", None):
+            for tuning in ("method=plain", "method=tstp,k=1", "method=tstp,k=3,c=1",
+                           "method=tstp,k=3,c=2", None):
                 got = gpu_sweep(u0, coeffs, shape, P, GAUSS_SEIDEL, DIRICHLET, T, tuning)
                 try:
                     assert_bitwise(got, ref, f"GS dims={dims} T={T} tuning={tuning}")
