@@ -156,7 +156,9 @@ int stencil_batch_run(int n, tvs_plan *const *plans, void *const *grids,
 
 /*
  * Autotune: time candidate schedules for this plan's problem on `grid`
- * (contents are restored afterwards) over T_probe steps, keep the fastest,
+ * (contents are restored afterwards) over T_probe steps -- or two bands of
+ * the candidate's depth if that is longer; candidates are compared per
+ * step -- keep the fastest,
  * record it in the tuning cache (path from TVS_TUNE_CACHE, if set), and
  * switch the plan to it.  Candidates that do not produce the same bits as
  * the first one are rejected (TVS_E_DEVICE).  best (may be NULL) receives

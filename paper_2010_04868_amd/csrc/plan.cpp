@@ -183,10 +183,10 @@ Schedule default_schedule(const Problem& p) {
     s.method = TVS_METHOD_TSTP;
     if (p.dependence == TVS_GAUSS_SEIDEL) {
         // sweeps per launch: more sweeps in flight hide the dependency waits
-        // (measured best 32..64 on 600^2 to 4096^2 grids).  One row per
-        // lane: two rows per lane halve the number of bands in flight and
-        // measured slower on both sizes (a tuner candidate only).
-        s.k = 32;
+        // (measured best 64 on 600^2 and 4096^2 grids).  One row per lane:
+        // two rows per lane halve the number of bands in flight and measured
+        // slower on both sizes (a tuner candidate only).
+        s.k = 64;
         s.c = 1;
         return s;
     }
@@ -195,9 +195,10 @@ Schedule default_schedule(const Problem& p) {
         s.pl = 64;
         s.k = 64;
         int64_t n = p.dims[0];
-        // enough pipelines to give every SIMD a few, but no shorter than the ramp
+        // short segments: many pipelines in flight (measured best 64 on
+        // 1e5 points), longer ones on long grids
         int64_t l = (n + 2047) / 2048;
-        s.l = (int)std::max<int64_t>(192, std::min<int64_t>(l, 4096));
+        s.l = (int)std::max<int64_t>(64, std::min<int64_t>(l, 4096));
         return s;
     }
     if (p.ndim == 2) {
@@ -211,21 +212,14 @@ Schedule default_schedule(const Problem& p) {
         while (s.w > 64 && s.w - 2 * s.k > 2 * p.dims[1]) s.w /= 2;
         if (s.w <= 2 * s.k) s.k = std::max(1, s.w / 4);
     } else {
-        // measured best on 512^3 star stencils: FP64 deeper bands on square
-        // tiles, FP32 shallow bands on wide tiles
-        if (f64) {
-            s.c = 8;
-            s.k = 4;
-            s.w = 32;
-            s.h = 32;
-            s.lanemap = 0;
-        } else {
-            s.c = 4;
-            s.k = 2;
-            s.w = 64;
-            s.h = 16;
-            s.lanemap = 1;
-        }
+        // measured best on 512^3 star stencils (FP64 and FP32): 4 levels on
+        // 32 x 32 tiles, 8 points per lane
+        s.c = 8;
+        s.k = 4;
+        s.w = 32;
+        s.h = 32;
+        s.lanemap = 0;
+        (void)f64;
         while (s.w > 16 && s.w - 2 * s.k > 2 * p.dims[2]) s.w /= 2;
         while (s.h > 8 && s.h - 2 * s.k > 2 * p.dims[1]) s.h /= 2;
         while (s.w <= 2 * s.k || s.h <= 2 * s.k) --s.k;

@@ -237,18 +237,23 @@ extern "C" int stencil_tune(tvs_plan* p, void* grid, const double* coeffs, int64
                 break;
             }
         }
-        // timed: restore + run, three times; keep the fastest
+        // timed: restore + run, three times; keep the fastest.  The timed run
+        // covers at least two full bands (k is capped by T, so a shorter probe
+        // would time a deep schedule as a shallow one), and candidates are
+        // compared per step, reported scaled to T_probe steps.
+        const int64_t kc = cands[i].method == TVS_METHOD_PLAIN ? 1 : std::max(1, cands[i].k);
+        const int64_t T_time = std::max<int64_t>(T_probe, 2 * kc);
         double ms_best = 1e300;
         for (int r = 0; r < 3; ++r) {
             (void)hipMemcpyAsync(grid, saved, bytes, hipMemcpyDeviceToDevice, st);
             (void)hipEventRecord(e0, st);
-            rc = enqueue_run(p, grid, coeffs, T_probe, st);
+            rc = enqueue_run(p, grid, coeffs, T_time, st);
             (void)hipEventRecord(e1, st);
             if (rc) break;
             (void)hipEventSynchronize(e1);
             float ms = 0;
             (void)hipEventElapsedTime(&ms, e0, e1);
-            ms_best = std::min(ms_best, (double)ms);
+            ms_best = std::min(ms_best, (double)ms * (double)T_probe / (double)T_time);
         }
         if (std::getenv("TVS_LOG"))
             std::fprintf(stderr, "[tvs tune] %s: %.4f ms\n", format_tuning(pr, cands[i]).c_str(),
