@@ -30,21 +30,23 @@ __device__ __forceinline__ T lane_value(T v, int m) {
     }
 }
 
-// The pipelines of one "tile": 4 waves of 64/PL pipelines each.  Lanes of
-// pipelines past the end return at once (whole pipelines only).
-template <typename T, bool PER, int PL>
-__device__ __forceinline__ void tstp1d_tile(const T* __restrict__ in, T* __restrict__ out,
-                                            const Args1d& a, const Coeffs<T>& cf, int tile,
-                                            int tid) {
-    const int lane = tid & 63;
-    const int j = lane % PL;  // lane j computes level j+1
-    const int64_t seg = ((int64_t)tile * 4 + (tid >> 6)) * (64 / PL) + lane / PL;
-    if (tid >= 256 || seg >= a.nseg) return;
+// One pipeline step body, specialised for whether the pipelines of this wave
+// touch a fixed end of the grid (interior waves carry no test for it).
+//
+// Output: the top level (lane k-1 of a pipeline) finishes one point per
+// step.  Every lane writes its value to LDS at a compile-time offset each
+// step -- lane k-1 into its pipeline's output row, the others into a scrap
+// area -- so no step needs a branch; after PL steps the wave reads the
+// output rows back (lane i: pipeline i / PL, step i % PL) and stores them
+// with one coalesced store.
+template <typename T, bool PER, int PL, bool BORDER>
+__device__ __forceinline__ void tstp1d_run(const T* __restrict__ in, T* __restrict__ out,
+                                           const Args1d& a, const Coeffs<T>& cf, int64_t s0,
+                                           int j, int lane, T* obuf, T* scrap) {
     const int k = a.k;
     const int64_t n = a.n;
-    const int64_t s0 = seg * a.Lv - k;  // global position of local position 0
     const int Lin = a.Lv + 2 * k;
-    const int Q = Lin + k - 1;          // steps until the last level has drained
+    const int Q = Lin + k - 1;  // steps until the last level has drained
     const T c0 = cf.c[0], c1 = cf.c[1], c2 = cf.c[2];
 
     auto load_block = [&](int blk) -> T {
@@ -54,6 +56,11 @@ __device__ __forceinline__ void tstp1d_tile(const T* __restrict__ in, T* __restr
         g = PER ? wrap_idx(g, n) : clamp_idx(g, n);
         return in[g];
     };
+    // lane k-1 writes its pipeline's output row; the rest write scrap
+    T* wbase = j == k - 1 ? obuf + (lane - j) : scrap + lane;
+    // read-back: lane i holds the output of pipeline i / PL at step i % PL
+    const int m_rd = lane % PL;
+    const int64_t s0_rd = s0;  // same pipeline as this lane
 
     T accA = 0, accB = 0, prev = 0, fin = 0;
     T cur = load_block(0);
@@ -68,25 +75,58 @@ __device__ __forceinline__ void tstp1d_tile(const T* __restrict__ in, T* __restr
                 const T inject = lane_value<PL>(cur, m);
                 // rotate + blend: lane j <- lane j-1's last output, lane 0 <- inject
                 const T v = shift_up<PL>(fin, inject);
-                const int pos = q - 2 * j;  // local position of v (level j)
-                T f = accB + c2 * v;        // level j+1 at pos-1: last term
-                accB = accA + c1 * v;       // level j+1 at pos: middle term
-                accA = c0 * v;              // level j+1 at pos+1: first term
-                if (!PER) {
+                T f = accB + c2 * v;   // level j+1 at pos-1: last term
+                accB = accA + c1 * v;  // level j+1 at pos: middle term
+                accA = c0 * v;         // level j+1 at pos+1: first term
+                if constexpr (BORDER) {
+                    const int pos = q - 2 * j;  // local position of v (level j)
                     const int64_t g = s0 + pos - 1;
                     if (g == 0 || g == n - 1) f = prev;  // fixed end
                 }
                 prev = v;
                 fin = f;
-                if (j == k - 1) {
-                    const int loc = pos - 1;
-                    const int64_t g = s0 + loc;
-                    if (loc >= k && loc < Lin - k && g < n) out[g] = f;
-                }
+                wbase[m] = f;
             }
         });
+        // store the top level's outputs of these PL steps
+        const int q = blk * PL + m_rd;
+        const int loc = q - 2 * (k - 1) - 1;
+        const int64_t g = s0_rd + loc;
+        const T r = obuf[lane];
+        if (q < Q && loc >= k && loc < Lin - k && g < n) out[g] = r;
         cur = nxt;
         nxt = after;
+    }
+}
+
+// The pipelines of one "tile": 4 waves of 64/PL pipelines each.  Lanes of
+// pipelines past the end return at once (whole pipelines only).
+template <typename T, bool PER, int PL>
+__device__ __forceinline__ void tstp1d_tile(const T* __restrict__ in, T* __restrict__ out,
+                                            const Args1d& a, const Coeffs<T>& cf, int tile,
+                                            int tid) {
+    // per wave: an output row per pipeline (64 slots) and 128 scrap slots
+    __shared__ T lds[4][64 + 128];
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int j = lane % PL;  // lane j computes level j+1
+    const int64_t seg0 = ((int64_t)tile * 4 + wave) * (64 / PL);  // first pipeline of the wave
+    const int64_t seg = seg0 + lane / PL;
+    if (tid >= 256 || seg >= a.nseg) return;
+    const int64_t s0 = seg * a.Lv - a.k;  // global position of local position 0
+    T* obuf = lds[wave];
+    T* scrap = lds[wave] + 64;
+    if constexpr (PER) {
+        tstp1d_run<T, PER, PL, false>(in, out, a, cf, s0, j, lane, obuf, scrap);
+    } else {
+        // the wave's pipelines read positions [seg0*Lv - k, (seg0 + 64/PL)*Lv + k)
+        const int64_t lo = seg0 * a.Lv - a.k;
+        const int64_t hi = (seg0 + 64 / PL) * (int64_t)a.Lv + a.k;
+        const bool border = lo <= 0 || hi >= a.n - 1;
+        if (border)
+            tstp1d_run<T, PER, PL, true>(in, out, a, cf, s0, j, lane, obuf, scrap);
+        else
+            tstp1d_run<T, PER, PL, false>(in, out, a, cf, s0, j, lane, obuf, scrap);
     }
 }
 
