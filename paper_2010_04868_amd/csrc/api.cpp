@@ -47,7 +47,7 @@ int ensure_scratch(tvs_plan* p) {
             p->scratch_bytes = need;
         }
     } else {
-        const size_t need = gs_work_bytes(p->prob, std::max(1, p->sched.k));
+        const size_t need = gs_work_bytes(p->prob);
         if (p->gs_work_bytes < need) {
             if (p->gs_work) (void)hipFree(p->gs_work);
             p->gs_work = nullptr;
@@ -55,7 +55,8 @@ int ensure_scratch(tvs_plan* p) {
             void* ptr = nullptr;
             if (hipMalloc(&ptr, need) != hipSuccess)
                 return set_error(TVS_E_NOMEM, "hipMalloc of the Gauss-Seidel work area failed");
-            if (hipMemset(ptr, 0, need) != hipSuccess)  // status word starts clear
+            // status word starts clear (each launch resets the rest of the state)
+            if (hipMemset(ptr, 0, gs_state_bytes(p->prob)) != hipSuccess)
                 return set_error(TVS_E_DEVICE, "hipMemset of the Gauss-Seidel work area failed");
             p->gs_work = ptr;
             p->gs_work_bytes = need;
@@ -110,13 +111,15 @@ int enqueue_jacobi(tvs_plan* p, void* grid, const CoeffBuf& cb, int64_t T, hipSt
 
 int enqueue_gs(tvs_plan* p, void* grid, const CoeffBuf& cb, int64_t T, hipStream_t st) {
     const int per_launch = p->sched.method == TVS_METHOD_PLAIN ? 1 : std::max(1, p->sched.k);
+    if (T <= 0) return TVS_OK;
+    TVS_HIP_TRY(gs_layout_in(p->prob, grid, p->gs_work, st));
     int64_t done = 0;
     while (done < T) {
         const int sw = (int)std::min<int64_t>(per_launch, T - done);
-        const int hr = p->sched.method == TVS_METHOD_PLAIN ? 1 : p->sched.c;
-        TVS_HIP_TRY(launch_gs(p->prob, grid, cb.bytes, sw, hr, p->gs_work, st));
+        TVS_HIP_TRY(launch_gs(p->prob, grid, cb.bytes, sw, p->gs_work, st));
         done += sw;
     }
+    TVS_HIP_TRY(gs_layout_out(p->prob, grid, p->gs_work, st));
     return TVS_OK;
 }
 

@@ -25,6 +25,14 @@
 //     release/acquire, which also orders memory across the XCDs' L2 caches;
 //   * every wait is bounded; on expiry the kernel records a status word and
 //     the remaining waits return at once, so the launch always drains.
+// Band layout: a run first copies the interior rows into a layout of its
+// own and copies them back at the end.  Band b holds its 64 rows column by
+// column, and row r is shifted right by SIG*r columns: element (x0+r, y) sits
+// at lay[((b*Wp) + y + SIG*r)*64 + r], Wp = n1 + 63*SIG.  The 64 points that
+// a wave updates in one step (row r at column c+1 = u - SIG*r) then share one
+// layout column and occupy 64 consecutive elements, so every load and store
+// of a step is one contiguous 512-byte (FP64) access instead of 64 accesses
+// to 64 rows.  The two fixed border rows are read from the grid itself.
 // Each point is updated exactly once per sweep, with the canonical operation
 // order, after all of its "new" and before any of its "old" neighbours are
 // overwritten, so the result is bit-identical to the naive lexicographic
@@ -50,6 +58,7 @@ struct GsArgs {
     int sweeps;   // sweeps in this launch
     int ncols;    // interior columns
     int nitems;
+    int Wp;       // layout columns per band row
     int* ticket;
     int* status;
     int* progress;  // [sweeps][nb]
@@ -95,68 +104,80 @@ __device__ void decode_item(int item, int nb, int sweeps, int* b, int* t) {
     }
 }
 
-// Value of lane 63 in every lane (wave-wide readlane).
+// Column y of the row above / below the band, in whichever array holds it.
 template <typename T>
-__device__ __forceinline__ T lane63(T v) {
-    if constexpr (sizeof(T) == 8) {
-        const long long b = __double_as_longlong(v);
-        const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), 63);
-        const int hi = __builtin_amdgcn_readlane((int)(b >> 32), 63);
-        return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
-    } else {
-        return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
-    }
-}
+struct GsRows {
+    const T* north;  // row x0-1: band b-1's last row in the layout, or grid row 0
+    int64_t nstride; // element step per column of `north`
+    const T* south;  // row x0+rows: band b+1's first row in the layout, or grid row n0-1
+    int64_t sstride;
+};
 
-// HR rows per lane: lane i owns rows x0+i, x0+64+i, ... of a band of 64*HR
-// rows.  The halves form one wavefront (half h runs 64*SIG columns behind
-// half h-1), so each lane carries HR independent dependency chains; the row
-// above the first row of half h is the last row of half h-1, whose value
-// comes from lane 63 by a readlane.
-template <typename T, bool BOX, int HR>
-__global__ __launch_bounds__(64) void gs2d(T* grid, GsArgs a, Coeffs<T> cf) {
+template <typename T, bool BOX>
+__global__ __launch_bounds__(64) void gs2d(T* grid, T* lay, GsArgs a, Coeffs<T> cf) {
     constexpr int SIG = BOX ? 2 : 1;
-    constexpr int BR = kRows * HR;  // rows per band
     const int lane = threadIdx.x;
-    const int64_t n1 = a.n1;
+    const int n1 = a.n1;
+    const int64_t Wp = a.Wp;
     for (;;) {
-        int item = 0;
-        if (lane == 0) item = atomicAdd(a.ticket, 1);
-        item = __shfl(item, 0);
+        // No branch on the lane index may sit in this loop: given a region
+        // that only lane 0 enters, the compiler may send lanes 1..63 round a
+        // shorter back edge that skips it, and they would then re-read a stale
+        // ticket without lane 0 and repeat an item forever.  So every lane
+        // joins the ticket atomic (lane 0 adds 1, the others 0) and the
+        // progress stores, and the ticket is made a scalar.
+        const int mine = atomicAdd(a.ticket, lane == 0 ? 1 : 0);
+        const int item = __builtin_amdgcn_readfirstlane(mine);
         if (item >= a.nitems) break;
         int b, t;
         decode_item(item, a.nb, a.sweeps, &b, &t);
-        const int x0 = 1 + BR * b;
-        const int rows = min(BR, a.n0 - 1 - x0);
-        const int L = rows - 1;  // last active row of the band
-        bool active[HR];
-        T* row[HR];
-        const T* row_s[HR];
-        // registers per half: west (new), centre/east (old), north and south histories
-        T Wv[HR], Cv[HR], Ev[HR], NWv[HR], Nv[HR], NEv[HR], SWv[HR], Sv[HR], SEv[HR], out[HR];
-#pragma unroll
-        for (int h = 0; h < HR; ++h) {
-            const int ri = kRows * h + lane;
-            active[h] = ri < rows;
-            const int xr = x0 + (active[h] ? ri : 0);  // safe row for inactive lanes
-            row[h] = grid + (int64_t)xr * n1;
-            row_s[h] = grid + (int64_t)(xr + 1) * n1;
-            Wv[h] = Cv[h] = out[h] = 0;
-            Ev[h] = row[h][0];
-            NWv[h] = Nv[h] = NEv[h] = grid[(int64_t)(xr - 1) * n1];
-            SWv[h] = Sv[h] = SEv[h] = row_s[h][0];
+        const int x0 = 1 + kRows * b;
+        const int rows = min(kRows, a.n0 - 1 - x0);
+        const int L = rows - 1;  // last row of the band
+        const bool active = lane < rows;
+        T* band = lay + (int64_t)b * Wp * kRows;
+        // neighbour rows of the band; column y of north is north[y * nstride]
+        GsRows<T> nb_;
+        if (b > 0) {
+            nb_.north = lay + ((int64_t)(b - 1) * Wp + SIG * (kRows - 1)) * kRows + (kRows - 1);
+            nb_.nstride = kRows;
+        } else {
+            nb_.north = grid;
+            nb_.nstride = 1;
         }
-        const T* row_n = grid + (int64_t)(x0 - 1) * n1;  // lane 0's north row
+        if (b + 1 < a.nb) {
+            nb_.south = lay + (int64_t)(b + 1) * Wp * kRows;
+            nb_.sstride = kRows;
+        } else {
+            nb_.south = grid + (int64_t)(a.n0 - 1) * n1;
+            nb_.sstride = 1;
+        }
+        // column y of this lane's row and of the row below it
+        auto own = [&](int y) -> T* { return band + (int64_t)(y + SIG * lane) * kRows + lane; };
+        auto below = [&](int y) -> const T* {
+            return lane < L ? band + (int64_t)(y + SIG * (lane + 1)) * kRows + lane + 1
+                            : nb_.south + (int64_t)y * nb_.sstride;
+        };
+        auto above = [&](int y) -> const T* {
+            return lane > 0 ? band + (int64_t)(y + SIG * (lane - 1)) * kRows + lane - 1
+                            : nb_.north + (int64_t)y * nb_.nstride;
+        };
+        // registers: west (new), centre/east (old), north and south histories
+        T Wv = 0, Cv = 0, out = 0;
+        T Ev = active ? *own(0) : T(0);
+        T NWv, Nv, NEv, SWv, Sv, SEv;
+        NWv = Nv = NEv = active ? *above(0) : T(0);
+        SWv = Sv = SEv = active ? *below(0) : T(0);
         int* prog_self = a.progress + t * a.nb + b;
         const int* prog_north = b > 0 ? a.progress + t * a.nb + (b - 1) : nullptr;
         const int* prog_prev = t > 0 ? a.progress + (t - 1) * a.nb + b : nullptr;
         const int* prog_south =
             (t > 0 && b + 1 < a.nb) ? a.progress + (t - 1) * a.nb + (b + 1) : nullptr;
 
-        // steps: row ri of the band is at column c = u - 1 - SIG*ri in [-1, ncols]
+        // steps: row i of the band is at column c = u - 1 - SIG*i in [-1, ncols]
         const int U = a.ncols + 2 + SIG * L;
         for (int us = 0; us < U; us += kSync) {
-          // columns the leading row (lane 0 of the first half) reaches in this interval
+          // columns the leading row (lane 0) reaches in this interval
           const int cmax = us + kSync - 2;
           if (prog_prev) wait_at_least(prog_prev, min(a.ncols, cmax + 2), a.status);
           if (prog_south) wait_at_least(prog_south, min(a.ncols, cmax + 2), a.status);
@@ -164,132 +185,209 @@ __global__ __launch_bounds__(64) void gs2d(T* grid, GsArgs a, Coeffs<T> cf) {
           // the producers' rows written before their progress stores are visible now
           __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
           for (int u0 = us; u0 < us + kSync && u0 < U; u0 += kBlock) {
-            T e_in[HR][kBlock], se_in[HR][kBlock], n_in[kBlock];
+            T e_in[kBlock], se_in[kBlock], n_in[kBlock];
 #pragma unroll
             for (int m = 0; m < kBlock; ++m) {
-#pragma unroll
-                for (int h = 0; h < HR; ++h) {
-                    const int c = u0 + m - 1 - SIG * (kRows * h + lane);
-                    const int ye = c + 2;
-                    e_in[h][m] = se_in[h][m] = 0;
-                    if (active[h] && c >= -1 && ye <= a.n1 - 1) {
-                        e_in[h][m] = row[h][ye];
-                        se_in[h][m] = row_s[h][ye];
-                    }
-                }
-                const int c0 = u0 + m - 1 - SIG * lane;
-                const int yn = c0 + SIG;
-                n_in[m] = 0;
-                if (lane == 0 && c0 >= -1 && yn <= a.n1 - 1) n_in[m] = row_n[yn];
+                const int c = u0 + m - 1 - SIG * lane;
+                const int ye = c + 2;
+                const bool ok = active && c >= -1 && ye <= n1 - 1;
+                // invalid lanes read a harmless in-band element and drop it
+                const T e = *(ok ? own(ye) : band);
+                const T se = *(ok ? below(ye) : band);
+                e_in[m] = ok ? e : T(0);
+                se_in[m] = ok ? se : T(0);
+                const int yn = c + SIG;
+                const bool okn = lane == 0 && c >= -1 && yn <= n1 - 1;
+                const T nv = *(okn ? above(yn) : band);
+                n_in[m] = okn ? nv : T(0);
             }
 #pragma unroll
             for (int m = 0; m < kBlock; ++m) {
                 // value of the row above, one column ahead of where the row
                 // above was last step: lane i-1's last output; for lane 0 the
-                // north row in memory (first half) or lane 63's last output of
-                // the half before (taken before this step updates it)
-                T nin[HR];
-                nin[0] = shift_up<64>(out[0], n_in[m]);
-#pragma unroll
-                for (int h = 1; h < HR; ++h) nin[h] = shift_up<64>(out[h], lane63(out[h - 1]));
-#pragma unroll
-                for (int h = 0; h < HR; ++h) {
-                    const int c = u0 + m - 1 - SIG * (kRows * h + lane);
-                    if (c >= -1 && c <= a.ncols) {
-                        if (BOX) {
-                            NWv[h] = Nv[h];
-                            Nv[h] = NEv[h];
-                            NEv[h] = nin[h];
-                            SWv[h] = Sv[h];
-                            Sv[h] = SEv[h];
-                            SEv[h] = se_in[h][m];
-                        } else {
-                            Nv[h] = nin[h];
-                            Sv[h] = SEv[h];
-                            SEv[h] = se_in[h][m];
-                        }
-                        Cv[h] = Ev[h];
-                        Ev[h] = e_in[h][m];
-                        T r = Cv[h];  // border columns pass their fixed value along
-                        if (c >= 0 && c < a.ncols) {
-                            if (BOX) {
-                                r = cf.c[0] * NWv[h];
-                                r = r + cf.c[1] * Nv[h];
-                                r = r + cf.c[2] * NEv[h];
-                                r = r + cf.c[3] * Wv[h];
-                                r = r + cf.c[4] * Cv[h];
-                                r = r + cf.c[5] * Ev[h];
-                                r = r + cf.c[6] * SWv[h];
-                                r = r + cf.c[7] * Sv[h];
-                                r = r + cf.c[8] * SEv[h];
-                            } else {
-                                r = cf.c[0] * Nv[h];
-                                r = r + cf.c[1] * Wv[h];
-                                r = r + cf.c[2] * Cv[h];
-                                r = r + cf.c[3] * Ev[h];
-                                r = r + cf.c[4] * Sv[h];
-                            }
-                            if (active[h]) row[h][c + 1] = r;
-                        }
-                        Wv[h] = r;
-                        out[h] = r;
+                // north row
+                const T nin = shift_up<64>(out, n_in[m]);
+                const int c = u0 + m - 1 - SIG * lane;
+                if (c >= -1 && c <= a.ncols) {
+                    if (BOX) {
+                        NWv = Nv;
+                        Nv = NEv;
+                        NEv = nin;
+                        SWv = Sv;
+                        Sv = SEv;
+                        SEv = se_in[m];
+                    } else {
+                        Nv = nin;
+                        Sv = SEv;
+                        SEv = se_in[m];
                     }
+                    Cv = Ev;
+                    Ev = e_in[m];
+                    T r = Cv;  // border columns pass their fixed value along
+                    if (c >= 0 && c < a.ncols) {
+                        if (BOX) {
+                            r = cf.c[0] * NWv;
+                            r = r + cf.c[1] * Nv;
+                            r = r + cf.c[2] * NEv;
+                            r = r + cf.c[3] * Wv;
+                            r = r + cf.c[4] * Cv;
+                            r = r + cf.c[5] * Ev;
+                            r = r + cf.c[6] * SWv;
+                            r = r + cf.c[7] * Sv;
+                            r = r + cf.c[8] * SEv;
+                        } else {
+                            r = cf.c[0] * Nv;
+                            r = r + cf.c[1] * Wv;
+                            r = r + cf.c[2] * Cv;
+                            r = r + cf.c[3] * Ev;
+                            r = r + cf.c[4] * Sv;
+                        }
+                        if (active) *own(c + 1) = r;
+                    }
+                    Wv = r;
+                    out = r;
                 }
             }
           }
           // publish the columns completed on the band's last row
           const int done = min(a.ncols, max(0, us + kSync - 1 - SIG * L));
           __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-          if (lane == 0) __hip_atomic_store(prog_self, done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          __hip_atomic_store(prog_self, done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-        if (lane == 0) __hip_atomic_store(prog_self, a.ncols, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(prog_self, a.ncols, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
 }
 
+// Grid <-> band layout, one 64 x 64 tile of (layout column, row) per
+// workgroup.  Row r of the tile covers grid columns starting at J - SIG*r,
+// so both the grid rows and the layout columns are accessed contiguously;
+// the tile passes through LDS (row stride 65 against bank conflicts).
+template <typename T, int SIG, bool IN>
+__global__ __launch_bounds__(256) void gs_layout(T* grid, T* lay, int n0, int n1, int64_t Wp,
+                                                 int ntiles) {
+    __shared__ T tile[kRows][kRows + 1];
+    const int b = blockIdx.x / ntiles;
+    const int J = (blockIdx.x % ntiles) * kRows;  // first layout column of the tile
+    const int x0 = 1 + kRows * b;
+    const int rows = min(kRows, n0 - 1 - x0);
+    const int tid = threadIdx.x;
+    T* band = lay + (int64_t)b * Wp * kRows;
+    if (IN) {
+        // grid rows -> tile[r][jj] = grid(x0+r, J + jj - SIG*r)
+        for (int e = tid; e < kRows * kRows; e += 256) {
+            const int r = e / kRows, jj = e % kRows;
+            const int y = J + jj - SIG * r;
+            if (r < rows && y >= 0 && y < n1) tile[r][jj] = grid[(int64_t)(x0 + r) * n1 + y];
+        }
+        __syncthreads();
+        // tile -> layout columns J + jj, rows contiguous
+        for (int e = tid; e < kRows * kRows; e += 256) {
+            const int jj = e / kRows, r = e % kRows;
+            const int y = J + jj - SIG * r;
+            if (r < rows && y >= 0 && y < n1 && J + jj < Wp)
+                band[(int64_t)(J + jj) * kRows + r] = tile[r][jj];
+        }
+    } else {
+        for (int e = tid; e < kRows * kRows; e += 256) {
+            const int jj = e / kRows, r = e % kRows;
+            const int y = J + jj - SIG * r;
+            if (r < rows && y >= 0 && y < n1 && J + jj < Wp)
+                tile[r][jj] = band[(int64_t)(J + jj) * kRows + r];
+        }
+        __syncthreads();
+        // interior columns only: the border columns never change
+        for (int e = tid; e < kRows * kRows; e += 256) {
+            const int r = e / kRows, jj = e % kRows;
+            const int y = J + jj - SIG * r;
+            if (r < rows && y >= 1 && y < n1 - 1) grid[(int64_t)(x0 + r) * n1 + y] = tile[r][jj];
+        }
+    }
+}
+
+// Work area: ticket, status word, progress counters for up to kMaxSweeps
+// sweeps per launch, then the band layout.
+constexpr int kMaxSweeps = 256;
+
+int bands_of(const Problem& p) { return (int)((p.dims[0] - 2 + kRows - 1) / kRows); }
+int64_t layout_width(const Problem& p) {
+    return p.dims[1] + (int64_t)(kRows - 1) * (p.shape == TVS_BOX ? 2 : 1);
+}
+size_t state_bytes(const Problem& p) {
+    const size_t raw = (size_t)(64 + (size_t)bands_of(p) * kMaxSweeps + 64) * sizeof(int);
+    return (raw + 255) / 256 * 256;
+}
+
 template <typename T>
-hipError_t launch_gs_t(const Problem& p, T* grid, const Coeffs<T>& cf, int sweeps, int hr,
-                       void* work, hipStream_t st) {
-    if (hr != 1 && hr != 2) return hipErrorInvalidValue;
+hipError_t launch_gs_t(const Problem& p, T* grid, const Coeffs<T>& cf, int sweeps, void* work,
+                       hipStream_t st) {
+    if (sweeps < 1 || sweeps > kMaxSweeps) return hipErrorInvalidValue;
     GsArgs a{};
     a.n0 = (int)p.dims[0];
     a.n1 = (int)p.dims[1];
     a.ncols = a.n1 - 2;
-    a.nb = (a.n0 - 2 + kRows * hr - 1) / (kRows * hr);
+    a.nb = bands_of(p);
     a.sweeps = sweeps;
     a.nitems = a.nb * sweeps;
+    a.Wp = (int)layout_width(p);
     int* w = (int*)work;
     a.ticket = w;
     a.status = w + 1;
     a.progress = w + 64;  // keep counters on their own cache lines
+    T* lay = (T*)((char*)work + state_bytes(p));
     const int nprog = a.nb * sweeps;
     hipLaunchKernelGGL(gs_reset, dim3((unsigned)std::min(1024, (nprog + 255) / 256 + 1)),
                        dim3(256), 0, st, a.ticket, a.progress, nprog);
     const int waves = std::min(a.nitems, 256 * 8);
-    if (p.shape == TVS_BOX) {
-        if (hr == 2) hipLaunchKernelGGL((gs2d<T, true, 2>), dim3(waves), dim3(64), 0, st, grid, a, cf);
-        else hipLaunchKernelGGL((gs2d<T, true, 1>), dim3(waves), dim3(64), 0, st, grid, a, cf);
-    } else {
-        if (hr == 2) hipLaunchKernelGGL((gs2d<T, false, 2>), dim3(waves), dim3(64), 0, st, grid, a, cf);
-        else hipLaunchKernelGGL((gs2d<T, false, 1>), dim3(waves), dim3(64), 0, st, grid, a, cf);
-    }
+    if (p.shape == TVS_BOX)
+        hipLaunchKernelGGL((gs2d<T, true>), dim3(waves), dim3(64), 0, st, grid, lay, a, cf);
+    else
+        hipLaunchKernelGGL((gs2d<T, false>), dim3(waves), dim3(64), 0, st, grid, lay, a, cf);
+    return hipGetLastError();
+}
+
+template <typename T, bool IN>
+hipError_t layout_t(const Problem& p, T* grid, void* work, hipStream_t st) {
+    const int64_t Wp = layout_width(p);
+    T* lay = (T*)((char*)work + state_bytes(p));
+    const int ntiles = (int)((Wp + kRows - 1) / kRows);
+    const int64_t nblk = (int64_t)ntiles * bands_of(p);
+    if (nblk > INT32_MAX) return hipErrorInvalidValue;
+    dim3 g((unsigned)nblk);
+    if (p.shape == TVS_BOX)
+        hipLaunchKernelGGL((gs_layout<T, 2, IN>), g, dim3(256), 0, st, grid, lay, (int)p.dims[0],
+                           (int)p.dims[1], Wp, ntiles);
+    else
+        hipLaunchKernelGGL((gs_layout<T, 1, IN>), g, dim3(256), 0, st, grid, lay, (int)p.dims[0],
+                           (int)p.dims[1], Wp, ntiles);
     return hipGetLastError();
 }
 
 }  // namespace
 
-size_t gs_work_bytes(const Problem& p, int sweeps) {
-    const int nb = (int)((p.dims[0] - 2 + kRows - 1) / kRows);
-    return (size_t)(64 + nb * sweeps + 64) * sizeof(int);
+size_t gs_state_bytes(const Problem& p) { return state_bytes(p); }
+
+size_t gs_work_bytes(const Problem& p) {
+    const size_t lay = (size_t)bands_of(p) * (size_t)layout_width(p) * kRows * p.elem_bytes();
+    return state_bytes(p) + lay;
 }
 
-hipError_t launch_gs(const Problem& p, void* grid, const void* coeffs, int sweeps, int hr,
-                     void* work, hipStream_t st) {
+hipError_t gs_layout_in(const Problem& p, const void* grid, void* work, hipStream_t st) {
+    if (p.dtype == TVS_F64) return layout_t<double, true>(p, (double*)grid, work, st);
+    return layout_t<float, true>(p, (float*)grid, work, st);
+}
+
+hipError_t gs_layout_out(const Problem& p, void* grid, void* work, hipStream_t st) {
+    if (p.dtype == TVS_F64) return layout_t<double, false>(p, (double*)grid, work, st);
+    return layout_t<float, false>(p, (float*)grid, work, st);
+}
+
+hipError_t launch_gs(const Problem& p, void* grid, const void* coeffs, int sweeps, void* work,
+                     hipStream_t st) {
     if (p.dtype == TVS_F64)
-        return launch_gs_t<double>(p, (double*)grid, *(const Coeffs<double>*)coeffs, sweeps, hr,
-                                   work, st);
-    return launch_gs_t<float>(p, (float*)grid, *(const Coeffs<float>*)coeffs, sweeps, hr, work,
-                              st);
+        return launch_gs_t<double>(p, (double*)grid, *(const Coeffs<double>*)coeffs, sweeps, work,
+                                   st);
+    return launch_gs_t<float>(p, (float*)grid, *(const Coeffs<float>*)coeffs, sweeps, work, st);
 }
 
 hipError_t gs_read_status(const void* work, int* status, hipStream_t st) {

@@ -40,12 +40,17 @@ bool band_geometry(const Problem& p, const Schedule& s, int k, BandGeom* g);
 hipError_t launch_tstp_band(const Problem& p, const BandGeom& g, const void* in, void* out,
                             const void* coeffs, hipStream_t st);
 
-// Gauss-Seidel: `sweeps` in-place sweeps of grid in one persistent launch,
-// `hr` (1 or 2) rows per lane.  `work` is device scratch of
-// gs_work_bytes(p, sweeps) bytes (enough for either hr).
-size_t gs_work_bytes(const Problem& p, int sweeps);
-hipError_t launch_gs(const Problem& p, void* grid, const void* coeffs, int sweeps, int hr,
-                     void* work, hipStream_t st);
+// Gauss-Seidel.  `work` is device scratch of gs_work_bytes(p) bytes whose
+// first gs_state_bytes(p) bytes are zero before its first launch.  A run is
+// gs_layout_in (interior rows of grid -> band layout in work), launch_gs
+// calls of up to 256 sweeps each (one persistent launch per call; the two
+// border rows are read from grid), and gs_layout_out (band layout -> grid).
+size_t gs_state_bytes(const Problem& p);
+size_t gs_work_bytes(const Problem& p);
+hipError_t gs_layout_in(const Problem& p, const void* grid, void* work, hipStream_t st);
+hipError_t launch_gs(const Problem& p, void* grid, const void* coeffs, int sweeps, void* work,
+                     hipStream_t st);
+hipError_t gs_layout_out(const Problem& p, void* grid, void* work, hipStream_t st);
 // Status word written by the Gauss-Seidel kernel (0 = ok) lives in `work`.
 hipError_t gs_read_status(const void* work, int* status, hipStream_t st);
 

@@ -183,9 +183,7 @@ Schedule default_schedule(const Problem& p) {
     s.method = TVS_METHOD_TSTP;
     if (p.dependence == TVS_GAUSS_SEIDEL) {
         // sweeps per launch: more sweeps in flight hide the dependency waits
-        // (measured best 64 on 600^2 and 4096^2 grids).  One row per lane:
-        // two rows per lane halve the number of bands in flight and measured
-        // slower on both sizes (a tuner candidate only).
+        // (measured best 64 on 600^2 and 4096^2 grids); one row per lane
         s.k = 64;
         s.c = 1;
         return s;
@@ -244,8 +242,8 @@ int check_schedule(const Problem& p, const Schedule& s) {
     if (s.k < 1) return set_error(TVS_E_INVALID, "k must be >= 1");
     if (p.dependence == TVS_GAUSS_SEIDEL) {
         if (s.k > 256) return set_error(TVS_E_INVALID, "k must be <= 256 for Gauss-Seidel");
-        if (s.c != 1 && s.c != 2)
-            return set_error(TVS_E_INVALID, "c (rows per lane) must be 1 or 2 for Gauss-Seidel");
+        if (s.c != 1)
+            return set_error(TVS_E_INVALID, "c (rows per lane) must be 1 for Gauss-Seidel");
         return TVS_OK;
     }
     if (s.s != 2)

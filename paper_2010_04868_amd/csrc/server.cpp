@@ -153,7 +153,7 @@ int size_request(Req* r) {
     r->grid_bytes = align_up(r->prob.bytes());
     r->aux_bytes = r->prob.dependence == TVS_JACOBI
                        ? align_up(r->prob.bytes())
-                       : align_up(gs_work_bytes(r->prob, std::max(1, r->plan->sched.k)));
+                       : align_up(gs_work_bytes(r->prob));
     r->footprint = r->grid_bytes + r->aux_bytes;
     return TVS_OK;
 }
@@ -171,7 +171,7 @@ int place_device(tvs_server* s, Req* r) {
         r->plan->gs_work = base + r->grid_bytes;
         r->plan->gs_work_bytes = r->aux_bytes;
         // the status word must start clear (each launch resets the rest)
-        if (hipMemsetAsync(r->plan->gs_work, 0, r->aux_bytes, s->stream) != hipSuccess)
+        if (hipMemsetAsync(r->plan->gs_work, 0, gs_state_bytes(r->prob), s->stream) != hipSuccess)
             return set_error(TVS_E_DEVICE, "clearing the Gauss-Seidel work area failed");
     }
     if (hipMemcpyAsync(r->dgrid, r->host.data(), r->prob.bytes(), hipMemcpyHostToDevice,

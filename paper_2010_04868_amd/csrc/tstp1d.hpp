@@ -14,22 +14,6 @@ struct Args1d {
     int64_t nseg;
 };
 
-template <int PL, typename T>
-__device__ __forceinline__ T lane_value(T v, int m) {
-    if constexpr (PL == 64) {
-        if constexpr (sizeof(T) == 8) {
-            long long b = __double_as_longlong(v);
-            int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), m);
-            int hi = __builtin_amdgcn_readlane((int)(b >> 32), m);
-            return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
-        } else {
-            return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), m));
-        }
-    } else {
-        return __shfl(v, m, PL);
-    }
-}
-
 // One pipeline step body, specialised for whether the pipelines of this wave
 // touch a fixed end of the grid (interior waves carry no test for it).
 //

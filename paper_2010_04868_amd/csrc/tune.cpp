@@ -89,13 +89,12 @@ std::vector<Schedule> tune_candidates(const Problem& p) {
     plain.method = TVS_METHOD_PLAIN;
     add(plain);
     if (p.dependence == TVS_GAUSS_SEIDEL) {
-        for (int c : {1, 2})
-            for (int k : {4, 8, 16, 32, 64}) {
-                Schedule s = base;
-                s.k = k;
-                s.c = c;
-                add(s);
-            }
+        for (int k : {4, 8, 16, 32, 64, 128}) {
+            Schedule s = base;
+            s.k = k;
+            s.c = 1;
+            add(s);
+        }
         return out;
     }
     if (p.ndim == 1) {

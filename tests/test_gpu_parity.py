@@ -73,7 +73,7 @@ def test_gauss_seidel_matches_oracle(shape, dtype):
         for T in (1, 2, 5, 9):
             ref = oracle_sweep(u0, coeffs, shape, P, GAUSS_SEIDEL, DIRICHLET, T)
             for tuning in ("method=plain", "method=tstp,k=1", "method=tstp,k=3,c=1",
-                           "method=tstp,k=3,c=2", None):
+                           "method=tstp,k=70", None):
                 got = gpu_sweep(u0, coeffs, shape, P, GAUSS_SEIDEL, DIRICHLET, T, tuning)
                 try:
                     assert_bitwise(got, ref, f"GS dims={dims} T={T} tuning={tuning}")
