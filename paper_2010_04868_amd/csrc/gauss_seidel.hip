@@ -44,12 +44,12 @@ namespace {
 
 constexpr int kRows = 64;        // rows per band (one wave)
 constexpr int kBlock = 8;        // steps whose loads are issued together
-// Steps between dependency checks and progress updates.  Crossing the XCDs'
-// separate L2 caches makes every agent-scope acquire and release expensive
-// (an L2 invalidate or write-back), so they are done once per kSync steps;
-// a dependent item then trails its producer by about kSync columns.
-constexpr int kSync = 64;
-static_assert(kSync % kBlock == 0, "sync interval");
+// Steps between dependency checks and progress updates (KS, a template
+// parameter chosen by row width).  Crossing the XCDs' separate L2 caches
+// makes every agent-scope acquire and release expensive (an L2 invalidate or
+// write-back), so they are done once per KS steps; a dependent item then
+// trails its producer by about KS columns.  Wide rows take 128 (fewer
+// fences), narrow ones 32 (shorter trails where little else is in flight).
 constexpr long long kSpinLimit = 1ll << 22;  // ~seconds: far beyond any legitimate wait
 
 struct GsArgs {
@@ -113,9 +113,10 @@ struct GsRows {
     int64_t sstride;
 };
 
-template <typename T, bool BOX>
+template <typename T, bool BOX, int KS>
 __global__ __launch_bounds__(64) void gs2d(T* grid, T* lay, GsArgs a, Coeffs<T> cf) {
     constexpr int SIG = BOX ? 2 : 1;
+    static_assert(KS % kBlock == 0, "sync interval");
     const int lane = threadIdx.x;
     const int n1 = a.n1;
     const int64_t Wp = a.Wp;
@@ -176,81 +177,99 @@ __global__ __launch_bounds__(64) void gs2d(T* grid, T* lay, GsArgs a, Coeffs<T> 
 
         // steps: row i of the band is at column c = u - 1 - SIG*i in [-1, ncols]
         const int U = a.ncols + 2 + SIG * L;
-        for (int us = 0; us < U; us += kSync) {
+        for (int us = 0; us < U; us += KS) {
           // columns the leading row (lane 0) reaches in this interval
-          const int cmax = us + kSync - 2;
+          const int cmax = us + KS - 2;
           if (prog_prev) wait_at_least(prog_prev, min(a.ncols, cmax + 2), a.status);
           if (prog_south) wait_at_least(prog_south, min(a.ncols, cmax + 2), a.status);
           if (prog_north) wait_at_least(prog_north, min(a.ncols, cmax + SIG), a.status);
           // the producers' rows written before their progress stores are visible now
           __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-          for (int u0 = us; u0 < us + kSync && u0 < U; u0 += kBlock) {
-            T e_in[kBlock], se_in[kBlock], n_in[kBlock];
+          // An inner interval keeps every lane (idle ones included) on an
+          // interior column, 0 <= c < ncols, for all of its steps: it needs no
+          // test per step, and idle lanes of a partial band store into their
+          // own unused row slots.
+          const bool inner = us >= 1 + SIG * (kRows - 1) && us + KS <= a.ncols + 1;
+          auto interval = [&](auto inner_t) {
+            constexpr bool IN = decltype(inner_t)::value;
+            for (int u0 = us; u0 < us + KS && (IN || u0 < U); u0 += kBlock) {
+              T e_in[kBlock], se_in[kBlock], n_in[kBlock];
 #pragma unroll
-            for (int m = 0; m < kBlock; ++m) {
-                const int c = u0 + m - 1 - SIG * lane;
-                const int ye = c + 2;
-                const bool ok = active && c >= -1 && ye <= n1 - 1;
-                // invalid lanes read a harmless in-band element and drop it
-                const T e = *(ok ? own(ye) : band);
-                const T se = *(ok ? below(ye) : band);
-                e_in[m] = ok ? e : T(0);
-                se_in[m] = ok ? se : T(0);
-                const int yn = c + SIG;
-                const bool okn = lane == 0 && c >= -1 && yn <= n1 - 1;
-                const T nv = *(okn ? above(yn) : band);
-                n_in[m] = okn ? nv : T(0);
-            }
+              for (int m = 0; m < kBlock; ++m) {
+                  const int c = u0 + m - 1 - SIG * lane;
+                  const int ye = c + 2;
+                  const int yn = c + SIG;
+                  if constexpr (IN) {
+                      e_in[m] = *own(ye);
+                      se_in[m] = *below(ye);
+                      n_in[m] = *above(yn);  // lane 0's value is the one used
+                  } else {
+                      const bool ok = active && c >= -1 && ye <= n1 - 1;
+                      // invalid lanes read a harmless in-band element and drop it
+                      const T e = *(ok ? own(ye) : band);
+                      const T se = *(ok ? below(ye) : band);
+                      e_in[m] = ok ? e : T(0);
+                      se_in[m] = ok ? se : T(0);
+                      const bool okn = lane == 0 && c >= -1 && yn <= n1 - 1;
+                      const T nv = *(okn ? above(yn) : band);
+                      n_in[m] = okn ? nv : T(0);
+                  }
+              }
 #pragma unroll
-            for (int m = 0; m < kBlock; ++m) {
-                // value of the row above, one column ahead of where the row
-                // above was last step: lane i-1's last output; for lane 0 the
-                // north row
-                const T nin = shift_up<64>(out, n_in[m]);
-                const int c = u0 + m - 1 - SIG * lane;
-                if (c >= -1 && c <= a.ncols) {
-                    if (BOX) {
-                        NWv = Nv;
-                        Nv = NEv;
-                        NEv = nin;
-                        SWv = Sv;
-                        Sv = SEv;
-                        SEv = se_in[m];
-                    } else {
-                        Nv = nin;
-                        Sv = SEv;
-                        SEv = se_in[m];
-                    }
-                    Cv = Ev;
-                    Ev = e_in[m];
-                    T r = Cv;  // border columns pass their fixed value along
-                    if (c >= 0 && c < a.ncols) {
-                        if (BOX) {
-                            r = cf.c[0] * NWv;
-                            r = r + cf.c[1] * Nv;
-                            r = r + cf.c[2] * NEv;
-                            r = r + cf.c[3] * Wv;
-                            r = r + cf.c[4] * Cv;
-                            r = r + cf.c[5] * Ev;
-                            r = r + cf.c[6] * SWv;
-                            r = r + cf.c[7] * Sv;
-                            r = r + cf.c[8] * SEv;
-                        } else {
-                            r = cf.c[0] * Nv;
-                            r = r + cf.c[1] * Wv;
-                            r = r + cf.c[2] * Cv;
-                            r = r + cf.c[3] * Ev;
-                            r = r + cf.c[4] * Sv;
-                        }
-                        if (active) *own(c + 1) = r;
-                    }
-                    Wv = r;
-                    out = r;
-                }
+              for (int m = 0; m < kBlock; ++m) {
+                  // value of the row above, one column ahead of where the row
+                  // above was last step: lane i-1's last output; for lane 0 the
+                  // north row
+                  const T nin = shift_up<64>(out, n_in[m]);
+                  const int c = u0 + m - 1 - SIG * lane;
+                  if (IN || (c >= -1 && c <= a.ncols)) {
+                      if (BOX) {
+                          NWv = Nv;
+                          Nv = NEv;
+                          NEv = nin;
+                          SWv = Sv;
+                          Sv = SEv;
+                          SEv = se_in[m];
+                      } else {
+                          Nv = nin;
+                          Sv = SEv;
+                          SEv = se_in[m];
+                      }
+                      Cv = Ev;
+                      Ev = e_in[m];
+                      T r = Cv;  // border columns pass their fixed value along
+                      if (IN || (c >= 0 && c < a.ncols)) {
+                          if (BOX) {
+                              r = cf.c[0] * NWv;
+                              r = r + cf.c[1] * Nv;
+                              r = r + cf.c[2] * NEv;
+                              r = r + cf.c[3] * Wv;
+                              r = r + cf.c[4] * Cv;
+                              r = r + cf.c[5] * Ev;
+                              r = r + cf.c[6] * SWv;
+                              r = r + cf.c[7] * Sv;
+                              r = r + cf.c[8] * SEv;
+                          } else {
+                              r = cf.c[0] * Nv;
+                              r = r + cf.c[1] * Wv;
+                              r = r + cf.c[2] * Cv;
+                              r = r + cf.c[3] * Ev;
+                              r = r + cf.c[4] * Sv;
+                          }
+                          if (IN || active) *own(c + 1) = r;
+                      }
+                      Wv = r;
+                      out = r;
+                  }
+              }
             }
-          }
+          };
+          if (inner)
+              interval(std::true_type{});
+          else
+              interval(std::false_type{});
           // publish the columns completed on the band's last row
-          const int done = min(a.ncols, max(0, us + kSync - 1 - SIG * L));
+          const int done = min(a.ncols, max(0, us + KS - 1 - SIG * L));
           __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
           __hip_atomic_store(prog_self, done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
@@ -339,10 +358,17 @@ hipError_t launch_gs_t(const Problem& p, T* grid, const Coeffs<T>& cf, int sweep
     hipLaunchKernelGGL(gs_reset, dim3((unsigned)std::min(1024, (nprog + 255) / 256 + 1)),
                        dim3(256), 0, st, a.ticket, a.progress, nprog);
     const int waves = std::min(a.nitems, 256 * 8);
-    if (p.shape == TVS_BOX)
-        hipLaunchKernelGGL((gs2d<T, true>), dim3(waves), dim3(64), 0, st, grid, lay, a, cf);
+    auto go = [&](auto kern) {
+        hipLaunchKernelGGL(kern, dim3(waves), dim3(64), 0, st, grid, lay, a, cf);
+    };
+    // sync interval by row width (measured on 600^2 and 4096^2 grids)
+    const bool box = p.shape == TVS_BOX;
+    if (a.ncols >= 2048)
+        box ? go(gs2d<T, true, 128>) : go(gs2d<T, false, 128>);
+    else if (a.ncols >= 512)
+        box ? go(gs2d<T, true, 64>) : go(gs2d<T, false, 64>);
     else
-        hipLaunchKernelGGL((gs2d<T, false>), dim3(waves), dim3(64), 0, st, grid, lay, a, cf);
+        box ? go(gs2d<T, true, 32>) : go(gs2d<T, false, 32>);
     return hipGetLastError();
 }
 

@@ -183,8 +183,8 @@ Schedule default_schedule(const Problem& p) {
     s.method = TVS_METHOD_TSTP;
     if (p.dependence == TVS_GAUSS_SEIDEL) {
         // sweeps per launch: more sweeps in flight hide the dependency waits
-        // (measured best 64 on 600^2 and 4096^2 grids); one row per lane
-        s.k = 64;
+        // (measured best 128 on 4096^2, 64 on 600^2); one row per lane
+        s.k = p.dims[1] - 2 >= 2048 ? 128 : 64;
         s.c = 1;
         return s;
     }
