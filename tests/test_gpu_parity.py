@@ -82,6 +82,27 @@ def test_gauss_seidel_matches_oracle(shape, dtype):
     assert not failures, "\n".join(failures[:20])
 
 
+@pytest.mark.parametrize("shape", [STAR, BOX])
+@pytest.mark.parametrize("dtype", [F64, F32])
+def test_gauss_seidel_wide_rows(shape, dtype):
+    # rows wide enough for interior intervals (no per-step tests) with each
+    # sync interval: 600 columns take intervals of 64 steps, 2100 of 128
+    P = npoints(2, shape)
+    coeffs = _coeffs(P, seed=50 + shape)
+    failures = []
+    for dims in [(70, 600), (131, 2100)]:
+        u0 = np.random.default_rng(sum(dims)).random(dims).astype(np_dtype(dtype))
+        for T in (1, 3, 7):
+            ref = oracle_sweep(u0, coeffs, shape, P, GAUSS_SEIDEL, DIRICHLET, T)
+            for tuning in ("method=plain", "method=tstp,k=2", None):
+                got = gpu_sweep(u0, coeffs, shape, P, GAUSS_SEIDEL, DIRICHLET, T, tuning)
+                try:
+                    assert_bitwise(got, ref, f"GS dims={dims} T={T} tuning={tuning}")
+                except AssertionError as e:
+                    failures.append(str(e))
+    assert not failures, "\n".join(failures[:20])
+
+
 def test_zero_steps_is_noop():
     u0 = np.random.default_rng(0).random((40, 50))
     got = gpu_sweep(u0, [1.0 / 9] * 9, BOX, 9, JACOBI, DIRICHLET, 0)
