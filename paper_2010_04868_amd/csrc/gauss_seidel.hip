@@ -32,7 +32,9 @@
 // a wave updates in one step (row r at column c+1 = u - SIG*r) then share one
 // layout column and occupy 64 consecutive elements, so every load and store
 // of a step is one contiguous 512-byte (FP64) access instead of 64 accesses
-// to 64 rows.  The two fixed border rows are read from the grid itself.
+// to 64 rows.  The top border row is read from the grid itself; the bottom
+// one is copied once into an extra band slot (row 0 of band nb), so that the
+// row below any band is in the layout with the same column stride.
 // Each point is updated exactly once per sweep, with the canonical operation
 // order, after all of its "new" and before any of its "old" neighbours are
 // overwritten, so the result is bit-identical to the naive lexicographic
@@ -146,13 +148,9 @@ __global__ __launch_bounds__(64) void gs2d(T* grid, T* lay, GsArgs a, Coeffs<T> 
             nb_.north = grid;
             nb_.nstride = 1;
         }
-        if (b + 1 < a.nb) {
-            nb_.south = lay + (int64_t)(b + 1) * Wp * kRows;
-            nb_.sstride = kRows;
-        } else {
-            nb_.south = grid + (int64_t)(a.n0 - 1) * n1;
-            nb_.sstride = 1;
-        }
+        // band b+1's first row, or the bottom border row in band slot nb
+        nb_.south = lay + (int64_t)(b + 1) * Wp * kRows;
+        nb_.sstride = kRows;
         // column y of this lane's row and of the row below it
         auto own = [&](int y) -> T* { return band + (int64_t)(y + SIG * lane) * kRows + lane; };
         auto below = [&](int y) -> const T* {
@@ -194,15 +192,24 @@ __global__ __launch_bounds__(64) void gs2d(T* grid, T* lay, GsArgs a, Coeffs<T> 
             constexpr bool IN = decltype(inner_t)::value;
             for (int u0 = us; u0 < us + KS && (IN || u0 < U); u0 += kBlock) {
               T e_in[kBlock], se_in[kBlock], n_in[kBlock];
+              // row below at column u0+1-SIG*lane, and lane 0's row above at
+              // column u0-1+SIG (the same address in every lane)
+              const T* bptr = lane < L ? band + (int64_t)(u0 + 1 + SIG) * kRows + lane + 1
+                                       : nb_.south + (int64_t)(u0 + 1 - SIG * lane) * kRows;
+              const T* nptr = nb_.north + (int64_t)(u0 - 1 + SIG) * nb_.nstride;
+              (void)bptr;
+              (void)nptr;
 #pragma unroll
               for (int m = 0; m < kBlock; ++m) {
                   const int c = u0 + m - 1 - SIG * lane;
                   const int ye = c + 2;
                   const int yn = c + SIG;
                   if constexpr (IN) {
-                      e_in[m] = *own(ye);
-                      se_in[m] = *below(ye);
-                      n_in[m] = *above(yn);  // lane 0's value is the one used
+                      // column strides are whole layout columns: one base per
+                      // block and immediate offsets
+                      e_in[m] = own(u0 + 1 - SIG * lane)[m * kRows];
+                      se_in[m] = bptr[m * kRows];
+                      n_in[m] = nptr[m * nb_.nstride];  // lane 0's value is the one used
                   } else {
                       const bool ok = active && c >= -1 && ye <= n1 - 1;
                       // invalid lanes read a harmless in-band element and drop it
@@ -324,6 +331,14 @@ __global__ __launch_bounds__(256) void gs_layout(T* grid, T* lay, int n0, int n1
     }
 }
 
+// The bottom border row (fixed) into band slot nb, row 0, without skew.
+template <typename T>
+__global__ __launch_bounds__(256) void gs_bottom_row(const T* grid, T* lay, int n0, int n1,
+                                                     int nb, int64_t Wp) {
+    const int y = blockIdx.x * 256 + threadIdx.x;
+    if (y < n1) lay[((int64_t)nb * Wp + y) * kRows] = grid[(int64_t)(n0 - 1) * n1 + y];
+}
+
 // Work area: ticket, status word, progress counters for up to kMaxSweeps
 // sweeps per launch, then the band layout.
 constexpr int kMaxSweeps = 256;
@@ -386,6 +401,9 @@ hipError_t layout_t(const Problem& p, T* grid, void* work, hipStream_t st) {
     else
         hipLaunchKernelGGL((gs_layout<T, 1, IN>), g, dim3(256), 0, st, grid, lay, (int)p.dims[0],
                            (int)p.dims[1], Wp, ntiles);
+    if (IN)
+        hipLaunchKernelGGL((gs_bottom_row<T>), dim3((unsigned)((p.dims[1] + 255) / 256)), dim3(256),
+                           0, st, grid, lay, (int)p.dims[0], (int)p.dims[1], bands_of(p), Wp);
     return hipGetLastError();
 }
 
@@ -394,7 +412,8 @@ hipError_t layout_t(const Problem& p, T* grid, void* work, hipStream_t st) {
 size_t gs_state_bytes(const Problem& p) { return state_bytes(p); }
 
 size_t gs_work_bytes(const Problem& p) {
-    const size_t lay = (size_t)bands_of(p) * (size_t)layout_width(p) * kRows * p.elem_bytes();
+    // nb bands and one slot for the bottom border row
+    const size_t lay = (size_t)(bands_of(p) + 1) * (size_t)layout_width(p) * kRows * p.elem_bytes();
     return state_bytes(p) + lay;
 }
 
