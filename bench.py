@@ -77,6 +77,7 @@ WORKLOADS = {
                      "3D 7-point star Jacobi FP32"),
     "heat1d": (lambda inp, n, T: inp.heat1d(**_kw(n, T)), "1D 3-point Jacobi FP64"),
     "gs2d5p": (lambda inp, n, T: inp.gs2d5p(**_kw(n, T)), "2D 5-point Gauss-Seidel FP64"),
+    "gs1d3p": (lambda inp, n, T: inp.gs1d3p(**_kw(n, T)), "1D 3-point Gauss-Seidel FP64"),
 }
 
 
@@ -121,7 +122,7 @@ def kernel_name(p, info, inputs) -> str:
     if info["method"] == 0:
         return "plain step"
     if p.dependence == inputs.GAUSS_SEIDEL:
-        return "gs2d wavefront"
+        return "gs1d sweep pipeline" if p.ndim == 1 else "gs2d wavefront"
     if p.ndim == 1:
         return "tstp1d"
     return "tstp_reg2d" if info.get("kern", 0) == 1 else "tstp_nd"

@@ -339,6 +339,94 @@ __global__ __launch_bounds__(256) void gs_bottom_row(const T* grid, T* lay, int 
     if (y < n1) lay[((int64_t)nb * Wp + y) * kRows] = grid[(int64_t)(n0 - 1) * n1 + y];
 }
 
+// 1D Gauss-Seidel: lanes are successive sweeps.  This is the paper's way of
+// vectorizing a Gauss-Seidel stencil (Section 3.4): a vector holds points of
+// different time steps, skewed along the space axis, and each lane runs the
+// sequential x-chain of its own sweep.  Global lane g = 64*w + j holds sweep
+// t0+g and updates x = q + 1 - 2g at its step q.  It needs the new value of
+// x-1 (its own last output) and the old values of x and x+1, which are lane
+// g-1's outputs of steps q-2 and q-1 (Section 3.2's legality rule with
+// s = 2).  Within a wave they arrive by DPP shifts; wave w's lane 0 takes
+// them from an LDS ring written by wave w-1's lane 63 (wave 0's ring holds
+// the grid itself: u[p] at slot p-3).  Wave w runs one block of 64 steps
+// behind wave w-1, so a ring slot is always written one barrier before it is
+// read; the ring keeps three blocks.  The last sweep's outputs go through
+// LDS and leave in one coalesced store per block.  Up to 16 waves: 1024
+// sweeps in one launch, in place (writes trail reads by 2k positions).
+template <typename T>
+__global__ __launch_bounds__(1024) void gs1d(T* u, int n, int k, Coeffs<T> cf) {
+    constexpr int R = 3 * 64;  // ring slots: three blocks of steps
+    __shared__ T ring[16][R];
+    __shared__ T scrap[16][256];  // destinations of lanes that hand nothing on
+    __shared__ T obuf[64];
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int W = (k + 63) / 64;  // waves of the workgroup
+    const int wl = (k - 1) / 64, jl = (k - 1) % 64;  // the last sweep's lane
+    const int g = 64 * w + lane;
+    const T ul = u[0], ur = u[n - 1];
+    const T c0 = cf.c[0], c1 = cf.c[1], c2 = cf.c[2];
+    const int b_end = ((n - 3) + 2 * (k - 1)) / 64;  // last block of the last sweep
+    const int NB = b_end + W;
+    T p1 = ul, p2 = ul;  // this lane's outputs of the last two steps
+    // wave 0: positions 1, 2 in slots R-2, R-1 and block 0 (positions 3..66)
+    T nxt = T(0);
+    if (w == 0) {
+        const int p = 3 + lane;
+        ring[0][lane] = p < n ? u[p] : T(0);
+        const int p2i = 1 + (lane & 1);
+        const T v2 = p2i < n ? u[p2i] : T(0);
+        ring[0][R - 2 + (lane & 1)] = v2;  // every lane writes one of the two slots
+        nxt = p + 64 < n ? u[p + 64] : T(0);
+    }
+    T* rout = (lane == 63 && w + 1 < W) ? &ring[w + 1][0] : &scrap[w][lane];
+    T* obase = (w == wl && lane == jl) ? obuf : &scrap[w][lane];
+    __syncthreads();
+    for (int B = 0; B < NB; ++B) {
+        const int b = B - w;
+        if (b >= 0 && b <= b_end) {
+            const int sb = (64 * b) % R;  // slot of step 64b
+            if (w == 0 && b > 0) {
+                ring[0][sb + lane] = nxt;  // positions 64b+3 .. 64b+66
+                const int p = 64 * (b + 1) + 3 + lane;
+                nxt = p < n ? u[p] : T(0);
+            }
+            const T* src = &ring[w][0];
+            // slots of steps 64b-2 and 64b-1
+            const int sm2 = (sb + R - 2) % R, sm1 = (sb + R - 1) % R;
+            T cin = src[sm2];
+            T ein = src[sm1];
+            static_for<0, 64>([&](auto mc) {
+                constexpr int m = decltype(mc)::value;
+                const int q = 64 * b + m;
+                // old values of x (lane g-1, step q-2) and x+1 (step q-1)
+                const T C = shift_up<64>(p2, cin);
+                T E = shift_up<64>(p1, ein);
+                const int x = q + 1 - 2 * g;
+                E = x == n - 2 ? ur : E;  // the right end is fixed
+                T f = c0 * p1;            // x-1: this sweep's new value
+                f = f + c1 * C;
+                f = f + c2 * E;
+                const bool valid = x >= 1 && x <= n - 2;
+                p2 = p1;
+                p1 = valid ? f : ul;
+                rout[sb + m] = p1;  // lane 63: the next wave's input
+                obase[m] = p1;      // the last sweep's lane: output row
+                cin = ein;
+                if constexpr (m + 1 < 64) ein = src[sb + m];  // slot of step q
+            });
+            if (w == wl) {
+                // the last sweep's outputs of this block: steps 64b + lane
+                const int x = 64 * b + lane + 1 - 2 * (k - 1);
+                const T r = obuf[lane];
+                if (x >= 1 && x <= n - 2) u[x] = r;
+            }
+        }
+        __syncthreads();
+    }
+}
+
 // Work area: ticket, status word, progress counters for up to kMaxSweeps
 // sweeps per launch, then the band layout.
 constexpr int kMaxSweeps = 256;
@@ -409,26 +497,41 @@ hipError_t layout_t(const Problem& p, T* grid, void* work, hipStream_t st) {
 
 }  // namespace
 
-size_t gs_state_bytes(const Problem& p) { return state_bytes(p); }
+size_t gs_state_bytes(const Problem& p) { return p.ndim == 1 ? 256 : state_bytes(p); }
 
 size_t gs_work_bytes(const Problem& p) {
+    if (p.ndim == 1) return 256;  // status word only
     // nb bands and one slot for the bottom border row
     const size_t lay = (size_t)(bands_of(p) + 1) * (size_t)layout_width(p) * kRows * p.elem_bytes();
     return state_bytes(p) + lay;
 }
 
 hipError_t gs_layout_in(const Problem& p, const void* grid, void* work, hipStream_t st) {
+    if (p.ndim == 1) return hipSuccess;  // the 1D kernel works on the grid itself
     if (p.dtype == TVS_F64) return layout_t<double, true>(p, (double*)grid, work, st);
     return layout_t<float, true>(p, (float*)grid, work, st);
 }
 
 hipError_t gs_layout_out(const Problem& p, void* grid, void* work, hipStream_t st) {
+    if (p.ndim == 1) return hipSuccess;
     if (p.dtype == TVS_F64) return layout_t<double, false>(p, (double*)grid, work, st);
     return layout_t<float, false>(p, (float*)grid, work, st);
 }
 
 hipError_t launch_gs(const Problem& p, void* grid, const void* coeffs, int sweeps, void* work,
                      hipStream_t st) {
+    if (p.ndim == 1) {
+        if (sweeps < 1 || sweeps > 1024 || p.dims[0] < 3) return hipErrorInvalidValue;
+        const dim3 block((unsigned)(64 * ((sweeps + 63) / 64)));
+        const int n = (int)p.dims[0];
+        if (p.dtype == TVS_F64)
+            hipLaunchKernelGGL((gs1d<double>), dim3(1), block, 0, st, (double*)grid, n, sweeps,
+                               *(const Coeffs<double>*)coeffs);
+        else
+            hipLaunchKernelGGL((gs1d<float>), dim3(1), block, 0, st, (float*)grid, n, sweeps,
+                               *(const Coeffs<float>*)coeffs);
+        return hipGetLastError();
+    }
     if (p.dtype == TVS_F64)
         return launch_gs_t<double>(p, (double*)grid, *(const Coeffs<double>*)coeffs, sweeps, work,
                                    st);

@@ -66,8 +66,8 @@ int validate(Problem* pr, int ndim, const int64_t* dims, int dtype, int shape, i
     if (r != 1) return set_error(TVS_E_UNSUPPORTED, "only radius 1 stencils are implemented");
     if (dependence == TVS_GAUSS_SEIDEL && boundary == TVS_PERIODIC)
         return set_error(TVS_E_UNSUPPORTED, "Gauss-Seidel with a periodic boundary");
-    if (dependence == TVS_GAUSS_SEIDEL && ndim != 2)
-        return set_error(TVS_E_UNSUPPORTED, "Gauss-Seidel is implemented for 2D grids");
+    if (dependence == TVS_GAUSS_SEIDEL && ndim == 3)
+        return set_error(TVS_E_UNSUPPORTED, "Gauss-Seidel is implemented for 1D and 2D grids");
     pr->ndim = ndim;
     for (int a = 0; a < 3; ++a) pr->dims[a] = a < ndim ? dims[a] : 1;
     pr->dtype = dtype;
@@ -182,9 +182,14 @@ Schedule default_schedule(const Problem& p) {
     Schedule s;
     s.method = TVS_METHOD_TSTP;
     if (p.dependence == TVS_GAUSS_SEIDEL) {
-        // sweeps per launch: more sweeps in flight hide the dependency waits
-        // (measured best 128 on 4096^2, 64 on 600^2); one row per lane
-        s.k = p.dims[1] - 2 >= 2048 ? 128 : 64;
+        // sweeps per launch.  1D: one lane per sweep, up to 16 waves (1024
+        // sweeps) in one launch.  2D: more sweeps in flight hide the
+        // dependency waits (measured best 128 on 4096^2, 64 on 600^2); one
+        // row per lane.
+        if (p.ndim == 1)
+            s.k = 1024;
+        else
+            s.k = p.dims[1] - 2 >= 2048 ? 128 : 64;
         s.c = 1;
         return s;
     }
@@ -241,7 +246,10 @@ int check_schedule(const Problem& p, const Schedule& s) {
     if (s.method == TVS_METHOD_PLAIN) return TVS_OK;
     if (s.k < 1) return set_error(TVS_E_INVALID, "k must be >= 1");
     if (p.dependence == TVS_GAUSS_SEIDEL) {
-        if (s.k > 256) return set_error(TVS_E_INVALID, "k must be <= 256 for Gauss-Seidel");
+        const int kmax = p.ndim == 1 ? 1024 : 256;
+        if (s.k > kmax)
+            return set_error(TVS_E_INVALID, "k must be <= " + std::to_string(kmax) +
+                                                " for Gauss-Seidel in " + std::to_string(p.ndim) + "D");
         if (s.c != 1)
             return set_error(TVS_E_INVALID, "c (rows per lane) must be 1 for Gauss-Seidel");
         return TVS_OK;

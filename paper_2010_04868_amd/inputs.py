@@ -120,6 +120,11 @@ def heat1d(periodic: bool = False, n: int = 100000, T: int = 1000) -> Problem:
                    JACOBI, PERIODIC if periodic else DIRICHLET, (0.25, 0.5, 0.25), T, 1)
 
 
+def gs1d3p(n: int = 100000, T: int = 1000) -> Problem:
+    """1D 3-point Gauss-Seidel in place, coefficients (1/4, 1/2, 1/4), fixed ends."""
+    return Problem("gs1d3p", (n,), F64, STAR, 3, GAUSS_SEIDEL, DIRICHLET, (0.25, 0.5, 0.25), T, 6)
+
+
 def box2d9p(dtype: int = F64, n: int = 8192, T: int = 1000) -> Problem:
     """2D 9-point box Jacobi, all coefficients 1/9, zero Dirichlet border."""
     return Problem("box2d9p" + ("_f32" if dtype == F32 else ""), (n, n), dtype, BOX, 9,

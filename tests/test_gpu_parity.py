@@ -103,6 +103,25 @@ def test_gauss_seidel_wide_rows(shape, dtype):
     assert not failures, "\n".join(failures[:20])
 
 
+@pytest.mark.parametrize("dtype", [F64, F32])
+def test_gauss_seidel_1d_matches_oracle(dtype):
+    # lanes are sweeps: 1, 3, 64 (one wave), 65 and 200 (chained waves) per launch
+    coeffs = _coeffs(3, seed=60)
+    failures = []
+    for n in (3, 5, 70, 1000, 4099):
+        u0 = np.random.default_rng(n).random(n).astype(np_dtype(dtype))
+        for T in (1, 5, 65, 130):
+            ref = oracle_sweep(u0, coeffs, STAR, 3, GAUSS_SEIDEL, DIRICHLET, T)
+            for tuning in ("method=plain", "method=tstp,k=1", "method=tstp,k=3",
+                           "method=tstp,k=64", "method=tstp,k=65", "method=tstp,k=200", None):
+                got = gpu_sweep(u0, coeffs, STAR, 3, GAUSS_SEIDEL, DIRICHLET, T, tuning)
+                try:
+                    assert_bitwise(got, ref, f"GS-1D n={n} T={T} tuning={tuning}")
+                except AssertionError as e:
+                    failures.append(str(e))
+    assert not failures, "\n".join(failures[:20])
+
+
 def test_zero_steps_is_noop():
     u0 = np.random.default_rng(0).random((40, 50))
     got = gpu_sweep(u0, [1.0 / 9] * 9, BOX, 9, JACOBI, DIRICHLET, 0)
