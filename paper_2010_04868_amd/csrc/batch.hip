@@ -457,6 +457,30 @@ constexpr size_t kMaxGraphs = 32;
 std::mutex g_graph_mu;
 std::map<std::vector<double>, GraphEntry> g_graphs;
 
+// Side streams on which a batch runs its Gauss-Seidel members next to the
+// captured Jacobi rounds and next to each other (each member is one chain of
+// dependent columns that fills little of the chip).  One set per device, kept
+// until the process ends; used under g_graph_mu.
+struct GsSide {
+    static constexpr int kAux = 4;
+    hipStream_t aux[kAux] = {};
+    hipEvent_t fork = nullptr;
+    hipEvent_t join[kAux] = {};
+};
+std::map<int, GsSide> g_gs_side;
+
+GsSide* gs_side(int dev) {
+    auto it = g_gs_side.find(dev);
+    if (it != g_gs_side.end()) return &it->second;
+    GsSide side;
+    bool ok = hipEventCreateWithFlags(&side.fork, hipEventDisableTiming) == hipSuccess;
+    for (int a = 0; ok && a < GsSide::kAux; ++a)
+        ok = hipStreamCreateWithFlags(&side.aux[a], hipStreamNonBlocking) == hipSuccess &&
+             hipEventCreateWithFlags(&side.join[a], hipEventDisableTiming) == hipSuccess;
+    if (!ok) return nullptr;  // members then run on the batch stream
+    return &g_gs_side.emplace(dev, side).first->second;
+}
+
 std::vector<double> layout_key(int n, tvs_plan* const* plans, void* const* grids,
                                const double* const* coeffs, const int64_t* T, int device) {
     std::vector<double> key;
@@ -551,15 +575,31 @@ int batch_run(int n, tvs_plan* const* plans, void* const* grids, const double* c
         e.plans.assign(plans, plans + n);
         it = g_graphs.emplace(std::move(key), std::move(e)).first;
     }
-    TVS_HIP_TRY(hipGraphLaunch(it->second.exec, st));
-    // Gauss-Seidel members run eagerly after the graph, on the same stream
-    for (const auto& m : it->second.bp.gs) {
+    // Gauss-Seidel members run eagerly (outside the graph) on side streams
+    // forked from the batch stream, concurrently with the Jacobi rounds, and
+    // are joined back before the batch stream continues
+    const auto& gs = it->second.bp.gs;
+    GsSide* side = gs.empty() ? nullptr : gs_side(dev);
+    if (side) {
+        TVS_HIP_TRY(hipEventRecord(side->fork, st));
+        for (int a = 0; a < GsSide::kAux; ++a)
+            TVS_HIP_TRY(hipStreamWaitEvent(side->aux[a], side->fork, 0));
+    }
+    int rc = TVS_OK;
+    for (size_t i = 0; i < gs.size() && rc == TVS_OK; ++i) {
+        const auto& m = gs[i];
         CoeffBuf cb;
         fill_coeffs(m.first->prob, coeffs[m.second], &cb);
-        int rc = enqueue_gs(m.first, grids[m.second], cb, T[m.second], st);
-        if (rc) return rc;
+        rc = enqueue_gs(m.first, grids[m.second], cb, T[m.second],
+                        side ? side->aux[i % GsSide::kAux] : st);
     }
-    return TVS_OK;
+    TVS_HIP_TRY(hipGraphLaunch(it->second.exec, st));
+    if (side)
+        for (int a = 0; a < GsSide::kAux; ++a) {
+            TVS_HIP_TRY(hipEventRecord(side->join[a], side->aux[a]));
+            TVS_HIP_TRY(hipStreamWaitEvent(st, side->join[a], 0));
+        }
+    return rc;
 }
 
 }  // namespace tvs
