@@ -25,6 +25,8 @@ MEMBERS = [
     ((66, 70), STAR, GAUSS_SEIDEL, DIRICHLET, F64, 6, "rand"),
     ((50, 60), BOX, JACOBI, DIRICHLET, F64, 0, "uni"),      # T = 0
     ((129, 130), BOX, JACOBI, DIRICHLET, F64, 17, "uni"),   # same variant as #2
+    ((500,), STAR, GAUSS_SEIDEL, DIRICHLET, F64, 11, "rand"),  # 1D Gauss-Seidel
+    ((131, 600), BOX, GAUSS_SEIDEL, DIRICHLET, F32, 5, "uni"),  # several on side streams
 ]
 
 
