@@ -42,6 +42,9 @@ def _load():
     lib.oracle_offsets.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                    ctypes.POINTER(ctypes.c_int)]
     lib.oracle_offsets.restype = ctypes.c_int
+    lib.oracle_life.argtypes = [ctypes.c_int64, ctypes.c_int64, ctypes.c_int, ctypes.c_int64,
+                                ctypes.POINTER(ctypes.c_int32)]
+    lib.oracle_life.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -87,4 +90,23 @@ def sweep(u: np.ndarray, coeffs: Sequence[float], shape: int, dependence: int, b
             c.ctypes.data_as(ctypes.POINTER(real)), int(T), g.ctypes.data_as(ctypes.POINTER(real)))
     if rc != 0:
         raise OracleError(f"oracle sweep failed ({rc})")
+    return g
+
+
+def life(u: np.ndarray, boundary: int, T: int) -> np.ndarray:
+    """Return the int32 board u after T steps of Game of Life B2S23 (the input is not modified).
+
+    The rule of the paper's Life stencil (Section 3.4): a dead cell becomes live
+    with exactly 2 live neighbours of 8, a live cell stays live with 2 or 3.  A
+    cell is live when non-zero; its neighbour count is the sum of the 8
+    neighbour values.  Dirichlet keeps the outer layer; periodic wraps.
+    """
+    lib = _load()
+    g = np.ascontiguousarray(u, dtype=np.int32).copy()
+    if g.ndim != 2:
+        raise OracleError("Life boards are 2D")
+    rc = lib.oracle_life(g.shape[0], g.shape[1], boundary, int(T),
+                         g.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
+    if rc != 0:
+        raise OracleError(f"oracle life failed ({rc})")
     return g

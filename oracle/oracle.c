@@ -42,7 +42,10 @@
  * Fourier and sine eigenmodes, the binomial closed form of the 1D 3-point
  * smoother, constant fields, fixed borders, translation invariance,
  * composition, the maximum principle, and the Gauss-Seidel/Jacobi
- * convergence factors of the discrete Laplacian.
+ * convergence factors of the discrete Laplacian.  The Game of Life sweep
+ * (below) is pinned by boards whose next state is derived by counting
+ * neighbours by hand, and by its invariants (fixed border, the square's
+ * symmetries, translation on the torus, composition).
  */
 #include <stddef.h>
 #include <stdint.h>
@@ -201,3 +204,47 @@ int NAME(int ndim, const int64_t *dims, int shape, int npoints, int dependence, 
 
 DEFINE_SWEEP(oracle_sweep_f64, double)
 DEFINE_SWEEP(oracle_sweep_f32, float)
+
+/*
+ * Game of Life, variant B2S23 -- the rule the paper adopts for its Life
+ * stencil (Section 3.4, "Game of life"): a 2D 9-point box stencil on integer
+ * cells where a dead cell becomes live when exactly 2 of its 8 neighbours are
+ * live and a live cell stays live when 2 or 3 are.  Cells are int32; a cell
+ * is live when it is non-zero, and its neighbour count is the sum of its 8
+ * neighbours' values (the number of live neighbours on a 0/1 board).  The new
+ * value is 1 or 0.  Jacobi: every cell of step t+1 reads step-t values.
+ * Dirichlet: the outer layer never changes; periodic: indices wrap.
+ */
+int oracle_life(int64_t n0, int64_t n1, int boundary, int64_t T, int32_t *u)
+{
+    if (n0 < 3 || n1 < 3 || T < 0 || !u) return -1;
+    if (boundary != 0 && boundary != 1) return -1;
+    const int64_t n = n0 * n1;
+    int32_t *v = (int32_t *)malloc((size_t)n * sizeof(int32_t));
+    if (!v) return -2;
+    int32_t *cur = u, *nxt = v;
+    for (int64_t t = 0; t < T; ++t) {
+        memcpy(nxt, cur, (size_t)n * sizeof(int32_t));
+        const int64_t lo = boundary == 1 ? 0 : 1;
+        for (int64_t i = lo; i < n0 - lo; ++i) {
+            for (int64_t j = lo; j < n1 - lo; ++j) {
+                int64_t s = 0;
+                for (int di = -1; di <= 1; ++di) {
+                    for (int dj = -1; dj <= 1; ++dj) {
+                        if (di == 0 && dj == 0) continue;
+                        const int64_t ii = wrap(i + di, n0), jj = wrap(j + dj, n1);
+                        s += cur[ii * n1 + jj];
+                    }
+                }
+                const int32_t c = cur[i * n1 + j];
+                nxt[i * n1 + j] = (s == 2 || (c != 0 && s == 3)) ? 1 : 0;
+            }
+        }
+        int32_t *tmp = cur;
+        cur = nxt;
+        nxt = tmp;
+    }
+    if (cur != u) memcpy(u, cur, (size_t)n * sizeof(int32_t));
+    free(v);
+    return 0;
+}

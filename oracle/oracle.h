@@ -13,6 +13,8 @@
 /* Canonical offsets (lexicographic, axis 0 most significant) as npoints rows
  * of ndim ints.  Returns the number of points, or a negative error code. */
 int oracle_offsets(int ndim, int shape, int npoints, int *offsets_out);
+/* Game of Life B2S23 on an n0 x n1 int32 board, T steps in place (0 = ok). */
+int oracle_life(int64_t n0, int64_t n1, int boundary, int64_t T, int32_t *u);
 
 /* T steps of the naive sweep on grid (C order, dims[0] slowest), in place.
  * Returns 0, or -1 bad argument, -2 point count inconsistent with the shape,

@@ -437,3 +437,70 @@ def test_gauss_seidel_fixed_point_is_laplace_solution():
                     b[k] += u[ii + 1, jj + 1]
     x = np.linalg.solve(A, b).reshape(m, m)
     assert np.max(np.abs(got[1:-1, 1:-1] - x)) < 1e-12
+
+
+# ---------------------------------------------------------------------------
+# Game of Life B2S23 (Section 3.4, "Game of life"): born with 2 live
+# neighbours of 8, survives with 2 or 3.  Expected boards below are derived by
+# counting neighbours by hand; none re-implements the rule.
+# ---------------------------------------------------------------------------
+def _board(shape, live):
+    b = np.zeros(shape, np.int32)
+    for r, c in live:
+        b[r, c] = 1
+    return b
+
+
+@pytest.mark.parametrize("boundary", [DIRICHLET, PERIODIC])
+def test_life_dead_board_stays_dead(boundary):
+    assert not oracle.life(np.zeros((9, 11), np.int32), boundary, 5).any()
+
+
+def test_life_lone_cell_dies_and_begets_nothing():
+    # the cell has no live neighbour; each of its 8 neighbours has exactly 1
+    got = oracle.life(_board((9, 9), [(4, 4)]), DIRICHLET, 1)
+    assert not got.any()
+
+
+def test_life_domino_moves_to_both_sides():
+    # live cells each see 1 neighbour and die; the 4 cells directly above and
+    # below the pair see both (2, born); every other cell sees at most 1
+    got = oracle.life(_board((8, 9), [(3, 4), (3, 5)]), DIRICHLET, 1)
+    want = _board((8, 9), [(2, 4), (2, 5), (4, 4), (4, 5)])
+    assert np.array_equal(got, want)
+
+
+def test_life_block_survives_and_grows_its_edges():
+    # each block cell sees the other 3 (survives); each of the 8 cells that
+    # share an edge with the block sees 2 (born); the 4 diagonal corners see 1
+    block = [(4, 4), (4, 5), (5, 4), (5, 5)]
+    edges = [(3, 4), (3, 5), (6, 4), (6, 5), (4, 3), (5, 3), (4, 6), (5, 6)]
+    got = oracle.life(_board((10, 10), block), DIRICHLET, 1)
+    assert np.array_equal(got, _board((10, 10), block + edges))
+
+
+def test_life_full_torus_dies():
+    # on a full periodic board every cell sees 8 live neighbours
+    assert not oracle.life(np.ones((6, 7), np.int32), PERIODIC, 1).any()
+
+
+def test_life_fixed_border_and_isotropy():
+    rng = np.random.default_rng(11)
+    u = (rng.random((23, 23)) < 0.4).astype(np.int32)
+    got = oracle.life(u, DIRICHLET, 6)
+    # the outer layer never changes
+    for edge in (np.s_[0, :], np.s_[-1, :], np.s_[:, 0], np.s_[:, -1]):
+        assert np.array_equal(got[edge], u[edge])
+    # the rule has the square's symmetries: transposes and mirror images commute with it
+    assert np.array_equal(oracle.life(u.T.copy(), DIRICHLET, 6), got.T)
+    assert np.array_equal(oracle.life(u[:, ::-1].copy(), DIRICHLET, 6), got[:, ::-1])
+
+
+def test_life_periodic_translation_and_composition():
+    rng = np.random.default_rng(12)
+    u = (rng.random((17, 19)) < 0.5).astype(np.int32)
+    got = oracle.life(u, PERIODIC, 7)
+    shifted = np.roll(np.roll(u, 5, axis=0), -3, axis=1)
+    assert np.array_equal(oracle.life(shifted, PERIODIC, 7),
+                          np.roll(np.roll(got, 5, axis=0), -3, axis=1))
+    assert np.array_equal(oracle.life(oracle.life(u, PERIODIC, 3), PERIODIC, 4), got)
