@@ -78,7 +78,13 @@ WORKLOADS = {
     "heat1d": (lambda inp, n, T: inp.heat1d(**_kw(n, T)), "1D 3-point Jacobi FP64"),
     "gs2d5p": (lambda inp, n, T: inp.gs2d5p(**_kw(n, T)), "2D 5-point Gauss-Seidel FP64"),
     "gs1d3p": (lambda inp, n, T: inp.gs1d3p(**_kw(n, T)), "1D 3-point Gauss-Seidel FP64"),
+    "life2d": (lambda inp, n, T: inp.life2d(**_kw(n, T)), "Game of Life B2S23, int32 cells"),
 }
+
+# Integer operations of one Life update by its definition: 7 additions for
+# the sum of 8 neighbours, and the rule (two equality tests, a non-zero test,
+# an and, an or).
+LIFE_OPS = 12
 
 
 def _kw(n, T):
@@ -91,6 +97,10 @@ def _kw(n, T):
 
 
 def describe(p, inputs) -> str:
+    if p.dtype == inputs.I32:
+        dims = "x".join(str(d) for d in p.dims)
+        bnd = "periodic" if p.boundary == inputs.PERIODIC else "dead fixed border"
+        return f"2D Game of Life B2S23 {dims} int32 cells, T={p.T}, {bnd}, cells live w.p. 1/2"
     kind = {(inputs.STAR, 3): "3-point", (inputs.STAR, 5): "5-point", (inputs.STAR, 7): "7-point",
             (inputs.BOX, 9): "9-point box"}.get((p.shape, p.order), f"{p.order}-point")
     dep = "Gauss-Seidel (in place, lexicographic)" if p.dependence == inputs.GAUSS_SEIDEL else \
@@ -133,12 +143,18 @@ def cpu_baseline(p, budget_s=15.0):
     import oracle
     from paper_2010_04868_amd import inputs
     u0 = inputs.make_grid(p)
+    if p.dtype == inputs.I32:
+        def sweep(u, steps):
+            return oracle.life(u, p.boundary, steps)
+    else:
+        def sweep(u, steps):
+            return oracle.sweep(u, p.coeffs, p.shape, p.dependence, p.boundary, steps)
     t0 = time.perf_counter()
-    u = oracle.sweep(u0, p.coeffs, p.shape, p.dependence, p.boundary, 1)
+    u = sweep(u0, 1)
     one = time.perf_counter() - t0
     steps = max(1, min(p.T, int(budget_s / max(one, 1e-6))))
     t0 = time.perf_counter()
-    oracle.sweep(u, p.coeffs, p.shape, p.dependence, p.boundary, steps)
+    sweep(u, steps)
     dt = time.perf_counter() - t0
     return {"value": round(p.updated_points() * steps / dt / 1e9, 4), "unit": "GStencil/s",
             "cores": 1, "kind": "oracle",
@@ -313,6 +329,7 @@ def main():
     log("plan:", info)
     nu = p.updated_points()
     eb = 8 if p.dtype == inputs.F64 else 4
+    life = p.dtype == inputs.I32
 
     # time-skewed solves; one setup run first (a repeated run is replayed from
     # a graph recorded on its second request, so that recording stays out of
@@ -330,7 +347,8 @@ def main():
     k = info["k"]
     band_ms = time_runs(torch, lambda: plan.run(grid, p.coeffs, 2 * k), 10) / 2
     band_updates = nu * k
-    flops = band_updates * (2 * p.order - 1)       # P products + (P-1) sums per update
+    # weighted: P products + (P-1) sums per update; Life: integer operations
+    flops = band_updates * (LIFE_OPS if life else 2 * p.order - 1)
     achieved_tops = flops / (band_ms / 1e3) / 1e12
     alg_bytes = 2 * eb * nu                          # each point read and written once per band
     achieved_gbs = alg_bytes / (band_ms / 1e3) / 1e9
@@ -349,7 +367,8 @@ def main():
     del grid
     torch.cuda.empty_cache()
 
-    peak = ALU_PEAK_TOPS if eb == 8 else ALU_PEAK_TOPS_F32
+    # int32 has no packed two-wide adds: the unpacked rate, as for FP64
+    peak = ALU_PEAK_TOPS if eb == 8 or life else ALU_PEAK_TOPS_F32
     traffic = profiled_traffic() if args.workload == "box2d9p" and args.n is None else None
     out = {
         "metric": METRIC,
@@ -362,8 +381,9 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if eb == 8 else "f32",
-        "data": f"synthetic: uniform[0,1) PCG64(seed {p.seed})",
+        "dtype": "i32" if life else ("f64" if eb == 8 else "f32"),
+        "data": (f"synthetic: 0/1 board, cells live w.p. 1/2, PCG64(seed {p.seed})" if life
+                 else f"synthetic: uniform[0,1) PCG64(seed {p.seed})"),
         "config": {"workload": describe(p, inputs),
                    "schedule": plan.tuning(),
                    "updated_points": nu},
@@ -374,7 +394,7 @@ def main():
                         "hbm_frac": round(plain_gbs / HBM_PEAK_GBS, 4),
                         "speedup": round(value / plain_value, 3)},
         "roofline": {"bound": "alu", "achieved": round(achieved_tops, 3),
-                     "peak": round(peak, 2), "unit": "TFLOP/s",
+                     "peak": round(peak, 2), "unit": "TOP/s (int32)" if life else "TFLOP/s",
                      "frac": round(achieved_tops / peak, 4),
                      "peak_unpacked": round(ALU_PEAK_TOPS, 2),
                      "traffic": traffic,

@@ -65,12 +65,17 @@ extern "C" {
 /* ---- enums ------------------------------------------------------------- */
 #define TVS_F32 0
 #define TVS_F64 1
+#define TVS_I32 2 /* int32 cells: Game of Life plans only (stencil_plan_life) */
 #define TVS_STAR 0
 #define TVS_BOX 1
 #define TVS_JACOBI 0
 #define TVS_GAUSS_SEIDEL 1
 #define TVS_DIRICHLET 0
 #define TVS_PERIODIC 1
+
+/* update rules: the weighted sum defined above, or Game of Life B2S23 */
+#define TVS_RULE_WEIGHTED 0
+#define TVS_RULE_LIFE 1
 
 /* execution methods a plan can use */
 #define TVS_METHOD_PLAIN 0 /* one time step per kernel launch (the baseline) */
@@ -97,6 +102,7 @@ typedef struct tvs_plan_info {
     int pl;            /* 1D: lanes per pipeline (16 or 64) */
     int kern;          /* 2D Jacobi: 0 = LDS level planes, 1 = register pipeline */
     char tuning[160];  /* the schedule as a tuning string that stencil_plan accepts */
+    int rule;          /* TVS_RULE_WEIGHTED or TVS_RULE_LIFE */
 } tvs_plan_info;
 
 /*
@@ -119,6 +125,33 @@ typedef struct tvs_plan_info {
 int stencil_plan(tvs_plan **out, int ndim, const int64_t *dims, int dtype, int shape, int order,
                  int dependence, int boundary, const char *tuning);
 
+/*
+ * Create a Game of Life plan: the B2S23 cellular automaton, one of the
+ * stencils the paper evaluates (Section 3.4 and Table 1, "Life": a 2D
+ * 9-point box stencil on integer cells).  One step, Jacobi-style (every cell
+ * of step t+1 reads step-t values):
+ *   s   = the sum of the values of the 8 neighbours (axis 0 and axis 1 offsets
+ *         in {-1, 0, 1}, the centre excluded), in 32-bit integer arithmetic;
+ *   new = 1 if s == 2, or if the cell is non-zero and s == 3; else 0.
+ * On a 0/1 board s is the number of live neighbours: a dead cell is born with
+ * exactly 2 of them and a live cell survives with 2 or 3.  Boards whose
+ * values lie within +-2^27 (0/1 boards in particular) never overflow the sum,
+ * so the result is that of the definition with exact integer sums.
+ *   ndim      must be 2
+ *   dims      2 storage extents, each >= 3
+ *   boundary  TVS_DIRICHLET: the outer layer of cells is never written (it
+ *             keeps any values it holds); TVS_PERIODIC: indices wrap
+ *   tuning    as for stencil_plan (2D Jacobi keys; kern=1 is not available)
+ * The plan has dtype TVS_I32, shape TVS_BOX, order 9, dependence TVS_JACOBI
+ * and rule TVS_RULE_LIFE.  stencil_run and stencil_tune take such a plan
+ * with coeffs NULL (any coeffs given are ignored); the grid is prod(dims)
+ * int32 values.  stencil_batch_run and the server do not take Life plans
+ * (TVS_E_UNSUPPORTED), and stencil_plan and stencil_run_simple reject
+ * TVS_I32 (TVS_E_INVALID).
+ */
+int stencil_plan_life(tvs_plan **out, int ndim, const int64_t *dims, int boundary,
+                      const char *tuning);
+
 /* Fill *info with the plan's problem and chosen schedule. */
 int stencil_plan_info(const tvs_plan *plan, tvs_plan_info *info);
 
@@ -131,7 +164,8 @@ int stencil_plan_destroy(tvs_plan *plan);
  *           input at step 0, output at step T (in place from the caller's
  *           view; Jacobi uses the plan's second buffer internally)
  *   coeffs  host array of P doubles in canonical offset order; rounded to
- *           FP32 (nearest even) for TVS_F32 plans; copied during the call
+ *           FP32 (nearest even) for TVS_F32 plans; copied during the call;
+ *           NULL (and ignored) for Life plans
  *   T       >= 0; T = 0 enqueues nothing
  *   stream  hipStream_t or NULL
  * One plan runs on one stream at a time; distinct plans may run concurrently.

@@ -12,14 +12,15 @@ from typing import List, Optional, Sequence
 
 from . import _lib
 from ._lib import StencilError, check
-from .inputs import (BOX, DIRICHLET, F32, F64, GAUSS_SEIDEL, JACOBI, PERIODIC, STAR, Problem,
-                     npoints)
+from .inputs import (BOX, DIRICHLET, F32, F64, GAUSS_SEIDEL, I32, JACOBI, PERIODIC, STAR,
+                     Problem, npoints)
 
 METHOD_PLAIN, METHOD_TSTP = 0, 1
+RULE_WEIGHTED, RULE_LIFE = 0, 1
 
-__all__ = ["Plan", "run", "run_simple", "batch_run", "Server", "StencilError", "load",
-           "STAR", "BOX", "JACOBI", "GAUSS_SEIDEL", "DIRICHLET", "PERIODIC", "F32", "F64",
-           "METHOD_PLAIN", "METHOD_TSTP", "version"]
+__all__ = ["Plan", "LifePlan", "run", "run_simple", "batch_run", "Server", "StencilError",
+           "load", "STAR", "BOX", "JACOBI", "GAUSS_SEIDEL", "DIRICHLET", "PERIODIC", "F32", "F64",
+           "I32", "METHOD_PLAIN", "METHOD_TSTP", "RULE_WEIGHTED", "RULE_LIFE", "version"]
 
 
 def load():
@@ -41,6 +42,8 @@ def _dtype_of(t) -> int:
         return F64
     if t.dtype == torch.float32:
         return F32
+    if t.dtype == torch.int32:
+        return I32
     raise TypeError(f"unsupported tensor dtype {t.dtype}")
 
 
@@ -73,6 +76,8 @@ class Plan:
 
     @classmethod
     def for_problem(cls, p: Problem, tuning: Optional[str] = None) -> "Plan":
+        if p.dtype == I32:
+            return LifePlan(p.dims, p.boundary, tuning)
         return cls(p.dims, p.dtype, p.shape, p.order, p.dependence, p.boundary, tuning)
 
     @property
@@ -91,19 +96,19 @@ class Plan:
         """The plan's schedule as a tuning string (accepted by ``Plan(..., tuning=)``)."""
         return self.info()["tuning"]
 
-    def run(self, grid, coeffs: Sequence[float], T: int, stream=None) -> None:
+    def run(self, grid, coeffs: Optional[Sequence[float]], T: int, stream=None) -> None:
         """Advance the device tensor ``grid`` by T steps, asynchronously on ``stream``."""
         if tuple(grid.shape) != self.dims or _dtype_of(grid) != self.dtype:
             raise ValueError("grid shape/dtype does not match the plan")
         if not grid.is_contiguous() or not grid.is_cuda:
             raise ValueError("grid must be a contiguous device tensor")
-        c = _coeff_array(coeffs)
+        c = None if coeffs is None else _coeff_array(coeffs)
         check(load().stencil_run(self._h, ctypes.c_void_p(grid.data_ptr()), c, int(T),
                                  ctypes.c_void_p(_stream_handle(stream))))
 
-    def tune(self, grid, coeffs: Sequence[float], T_probe: int, stream=None) -> str:
+    def tune(self, grid, coeffs: Optional[Sequence[float]], T_probe: int, stream=None) -> str:
         buf = ctypes.create_string_buffer(256)
-        c = _coeff_array(coeffs)
+        c = None if coeffs is None else _coeff_array(coeffs)
         check(load().stencil_tune(self._h, ctypes.c_void_p(grid.data_ptr()), c, int(T_probe),
                                   ctypes.c_void_p(_stream_handle(stream)), buf, 256))
         return buf.value.decode()
@@ -118,6 +123,29 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+
+class LifePlan(Plan):
+    """Game of Life B2S23 on an int32 board (``stencil_plan_life``): the 2D
+    9-point box neighbourhood, Jacobi dependence, no weights."""
+
+    def __init__(self, dims: Sequence[int], boundary: int = DIRICHLET,
+                 tuning: Optional[str] = None):
+        lib = load()
+        self._h = ctypes.c_void_p()
+        d = (ctypes.c_int64 * len(dims))(*[int(x) for x in dims])
+        check(lib.stencil_plan_life(ctypes.byref(self._h), len(dims), d, int(boundary),
+                                    tuning.encode() if tuning else None))
+        self.dims = tuple(int(x) for x in dims)
+        self.dtype, self.shape, self.order = I32, BOX, 9
+        self.dependence, self.boundary = JACOBI, boundary
+
+    def run(self, grid, coeffs=None, T: int = 0, stream=None) -> None:
+        """Advance the int32 device tensor ``grid`` by T generations (``coeffs`` is ignored)."""
+        super().run(grid, None, T, stream)
+
+    def tune(self, grid, coeffs=None, T_probe: int = 1, stream=None) -> str:
+        return super().tune(grid, None, T_probe, stream)
 
 
 def run(problem: Problem, grid, T: Optional[int] = None, tuning: Optional[str] = None,

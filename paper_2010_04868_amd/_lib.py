@@ -32,6 +32,7 @@ class PlanInfo(ctypes.Structure):
         ("tile_h", ctypes.c_int), ("tile_l", ctypes.c_int), ("lane_c", ctypes.c_int),
         ("lanemap", ctypes.c_int), ("scratch_bytes", ctypes.c_size_t),
         ("pl", ctypes.c_int), ("kern", ctypes.c_int), ("tuning", ctypes.c_char * 160),
+        ("rule", ctypes.c_int),
     ]
 
 
@@ -58,6 +59,8 @@ SIGNATURES = [
     ("stencil_plan", ctypes.c_int, [ctypes.POINTER(vp), ctypes.c_int, ctypes.POINTER(i64),
                                     ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                     ctypes.c_int, ctypes.c_char_p]),
+    ("stencil_plan_life", ctypes.c_int, [ctypes.POINTER(vp), ctypes.c_int, ctypes.POINTER(i64),
+                                         ctypes.c_int, ctypes.c_char_p]),
     ("stencil_plan_info", ctypes.c_int, [vp, ctypes.POINTER(PlanInfo)]),
     ("stencil_plan_destroy", ctypes.c_int, [vp]),
     ("stencil_run", ctypes.c_int, [vp, vp, dp, i64, vp]),

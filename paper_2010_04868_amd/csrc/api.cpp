@@ -23,7 +23,9 @@ static Coeffs<T> make_coeffs(const double* c, int P) {
 }
 
 void fill_coeffs(const Problem& p, const double* c, CoeffBuf* out) {
-    if (p.dtype == TVS_F64) {
+    if (p.rule == TVS_RULE_LIFE) {  // no weights
+        std::memset(out->bytes, 0, sizeof out->bytes);
+    } else if (p.dtype == TVS_F64) {
         auto k = make_coeffs<double>(c, p.order);
         std::memcpy(out->bytes, &k, sizeof k);
     } else {
@@ -227,17 +229,10 @@ int run_graph(tvs_plan* p, void* grid, const double* coeffs, int64_t T, hipStrea
     return TVS_OK;
 }
 
-}  // namespace tvs
-
-extern "C" {
-
-int stencil_plan(tvs_plan** out, int ndim, const int64_t* dims, int dtype, int shape, int order,
-                 int dependence, int boundary, const char* tuning) {
-    clear_error();
-    if (!out) return set_error(TVS_E_INVALID, "out is NULL");
-    Problem pr;
-    int rc = validate(&pr, ndim, dims, dtype, shape, order, dependence, boundary);
-    if (rc) return rc;
+// Schedule a validated problem (tuning string, else the tuning cache, else
+// the model's default) and create its plan.
+int make_plan(tvs_plan** out, const Problem& pr, const char* tuning) {
+    int rc = TVS_OK;
     Schedule s = default_schedule(pr);
     if (tuning && *tuning) {
         bool has_method = false;
@@ -260,6 +255,30 @@ int stencil_plan(tvs_plan** out, int ndim, const int64_t* dims, int dtype, int s
     p->sched = s;
     *out = p;
     return TVS_OK;
+}
+
+}  // namespace tvs
+
+extern "C" {
+
+int stencil_plan(tvs_plan** out, int ndim, const int64_t* dims, int dtype, int shape, int order,
+                 int dependence, int boundary, const char* tuning) {
+    clear_error();
+    if (!out) return set_error(TVS_E_INVALID, "out is NULL");
+    Problem pr;
+    int rc = validate(&pr, ndim, dims, dtype, shape, order, dependence, boundary);
+    if (rc) return rc;
+    return make_plan(out, pr, tuning);
+}
+
+int stencil_plan_life(tvs_plan** out, int ndim, const int64_t* dims, int boundary,
+                      const char* tuning) {
+    clear_error();
+    if (!out) return set_error(TVS_E_INVALID, "out is NULL");
+    Problem pr;
+    int rc = validate_life(&pr, ndim, dims, boundary);
+    if (rc) return rc;
+    return make_plan(out, pr, tuning);
 }
 
 int stencil_plan_info(const tvs_plan* p, tvs_plan_info* info) {
@@ -285,6 +304,7 @@ int stencil_plan_info(const tvs_plan* p, tvs_plan_info* info) {
     info->scratch_bytes = p->scratch_bytes + p->gs_work_bytes;
     info->pl = p->sched.pl;
     info->kern = p->sched.kern;
+    info->rule = p->prob.rule;
     std::snprintf(info->tuning, sizeof info->tuning, "%s", format_tuning(p->prob, p->sched).c_str());
     return TVS_OK;
 }
@@ -307,7 +327,10 @@ int stencil_plan_destroy(tvs_plan* p) {
 
 int stencil_run(tvs_plan* p, void* grid, const double* coeffs, int64_t T, void* stream) {
     clear_error();
-    if (!p || !grid || !coeffs) return set_error(TVS_E_INVALID, "NULL argument");
+    if (!p || !grid) return set_error(TVS_E_INVALID, "NULL argument");
+    static const double kNoWeights[kMaxPoints] = {};
+    if (p->prob.rule == TVS_RULE_LIFE) coeffs = kNoWeights;  // the rule has no weights
+    if (!coeffs) return set_error(TVS_E_INVALID, "NULL argument");
     if (T < 0) return set_error(TVS_E_INVALID, "T < 0");
     if (T == 0) return TVS_OK;
     if (p->prob.dependence == TVS_JACOBI) {

@@ -614,6 +614,8 @@ extern "C" int stencil_batch_run(int n, tvs_plan* const* plans, void* const* gri
     if (!plans || !grids || !coeffs || !T) return set_error(TVS_E_INVALID, "NULL argument");
     if (n > 60000) return set_error(TVS_E_INVALID, "batch larger than 60000 grids");
     for (int i = 0; i < n; ++i) {
+        if (plans[i] && plans[i]->prob.rule == TVS_RULE_LIFE)
+            return set_error(TVS_E_UNSUPPORTED, "Game of Life plans do not run in batches");
         if (!plans[i] || !grids[i] || !coeffs[i]) return set_error(TVS_E_INVALID, "NULL member");
         if (T[i] < 0) return set_error(TVS_E_INVALID, "T < 0");
     }

@@ -30,6 +30,7 @@ struct Problem {
     int dtype = TVS_F64, shape = TVS_STAR, order = 0, dependence = TVS_JACOBI,
         boundary = TVS_DIRICHLET;
     int radius = 1;
+    int rule = TVS_RULE_WEIGHTED;  // TVS_RULE_LIFE: B2S23 on int32 cells (2D box, Jacobi)
     int64_t elems() const {
         int64_t n = 1;
         for (int a = 0; a < ndim; ++a) n *= dims[a];

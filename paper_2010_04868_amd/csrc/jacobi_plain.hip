@@ -68,6 +68,43 @@ __global__ __launch_bounds__(256) void plain2d(const T* __restrict__ in, T* __re
     }
 }
 
+// Game of Life B2S23 (Section 3.4): the 2D 9-point box neighbourhood with
+// the B2S23 rule in place of a weighted sum.  Same strip walk as plain2d.
+// Sums are taken in unsigned 32-bit arithmetic (defined wrap-around; equal
+// to the signed sum whenever that does not overflow).
+template <bool PER, int RY>
+__global__ __launch_bounds__(256) void plain_life(const uint32_t* __restrict__ in,
+                                                  uint32_t* __restrict__ out, int n0, int n1) {
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= n1) return;
+    const int y0 = blockIdx.y * RY;
+    const int xm = PER ? (x == 0 ? n1 - 1 : x - 1) : max(x - 1, 0);
+    const int xp = PER ? (x == n1 - 1 ? 0 : x + 1) : min(x + 1, n1 - 1);
+    const bool col_border = !PER && (x == 0 || x == n1 - 1);
+    uint32_t w[RY + 2][3];
+#pragma unroll
+    for (int r = 0; r < RY + 2; ++r) {
+        const int y = y0 - 1 + r;
+        const int yy = PER ? (int)wrap_idx(y, n0) : (int)clamp_idx(y, n0);
+        const uint32_t* row = in + (int64_t)yy * n1;
+        w[r][0] = row[xm];
+        w[r][1] = row[x];
+        w[r][2] = row[xp];
+    }
+#pragma unroll
+    for (int r = 0; r < RY; ++r) {
+        const int y = y0 + r;
+        if (y < n0) {
+            const uint32_t c = w[r + 1][1];
+            const uint32_t s = w[r][0] + w[r][1] + w[r][2] + w[r + 1][0] + w[r + 1][2] +
+                               w[r + 2][0] + w[r + 2][1] + w[r + 2][2];
+            uint32_t nv = (s == 2u || (c != 0u && s == 3u)) ? 1u : 0u;
+            if (!PER && (col_border || y == 0 || y == n0 - 1)) nv = c;
+            out[(int64_t)y * n1 + x] = nv;
+        }
+    }
+}
+
 // 3D: thread = one (y, x) column, `RZ` planes, all loads issued first.
 template <typename T, bool BOX, bool PER, int RZ>
 __global__ __launch_bounds__(256) void plain3d(const T* __restrict__ in, T* __restrict__ out,
@@ -173,6 +210,18 @@ hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t st)
 
 hipError_t launch_plain_step(const Problem& p, const void* in, void* out, const void* coeffs,
                              hipStream_t st) {
+    if (p.rule == TVS_RULE_LIFE) {
+        const int n0 = (int)p.dims[0], n1 = (int)p.dims[1];
+        constexpr int ry = 8;
+        dim3 grid((unsigned)((n1 + 255) / 256), (unsigned)((n0 + ry - 1) / ry));
+        if (p.boundary == TVS_PERIODIC)
+            hipLaunchKernelGGL((plain_life<true, ry>), grid, dim3(256), 0, st,
+                               (const uint32_t*)in, (uint32_t*)out, n0, n1);
+        else
+            hipLaunchKernelGGL((plain_life<false, ry>), grid, dim3(256), 0, st,
+                               (const uint32_t*)in, (uint32_t*)out, n0, n1);
+        return hipGetLastError();
+    }
     if (p.dtype == TVS_F64)
         return plain_step_t<double>(p, (const double*)in, (double*)out,
                                     *(const Coeffs<double>*)coeffs, st);

@@ -38,7 +38,7 @@ bool band_geometry(const Problem& p, const Schedule& s, int k, BandGeom* g) {
         (p.ndim == 3 ? p.dims[1] * p.dims[2] : p.dims[1]) * (int64_t)p.elem_bytes();
     if (plane_bytes >= (int64_t(1) << 31)) return false;
     r.C = s.c;
-    if (p.ndim == 2 && s.kern == 1 && k == s.k) {
+    if (p.ndim == 2 && s.kern == 1 && k == s.k && p.rule != TVS_RULE_LIFE) {
         // register pipeline: a wave is a tile of 64*C columns, 4 tiles per workgroup
         if (!reg2d_supported(p.dtype, k, r.C)) return false;
         r.kern = 1;
@@ -95,6 +95,8 @@ hipError_t launch_tstp_band(const Problem& p, const BandGeom& g, const void* in,
             for (int q = 0; q < p.order; ++q) cd[q] = ((const Coeffs<float>*)coeffs)->c[q];
         return launch_reg2d(p, g, in, out, coeffs, all_equal(cd, p.order), st);
     }
+    if (p.rule == TVS_RULE_LIFE)
+        return launch_nd_life_2d(p, g, (const uint32_t*)in, (uint32_t*)out, st);
     if (p.dtype == TVS_F64) {
         auto& cf = *(const Coeffs<double>*)coeffs;
         double cd[kMaxPoints];

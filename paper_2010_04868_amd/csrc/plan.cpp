@@ -42,6 +42,8 @@ int validate(Problem* pr, int ndim, const int64_t* dims, int dtype, int shape, i
              int dependence, int boundary) {
     if (!dims) return set_error(TVS_E_INVALID, "dims is NULL");
     if (ndim < 1 || ndim > 3) return set_error(TVS_E_SHAPE, "ndim must be 1, 2 or 3");
+    if (dtype == TVS_I32)
+        return set_error(TVS_E_INVALID, "int32 grids are Game of Life boards: use stencil_plan_life");
     if (dtype != TVS_F32 && dtype != TVS_F64) return set_error(TVS_E_INVALID, "bad dtype");
     if (shape != TVS_STAR && shape != TVS_BOX) return set_error(TVS_E_INVALID, "bad shape");
     if (dependence != TVS_JACOBI && dependence != TVS_GAUSS_SEIDEL)
@@ -76,6 +78,17 @@ int validate(Problem* pr, int ndim, const int64_t* dims, int dtype, int shape, i
     pr->dependence = dependence;
     pr->boundary = boundary;
     pr->radius = r;
+    return TVS_OK;
+}
+
+// Game of Life B2S23 (Section 3.4, Table 1): a 2D 9-point box problem with
+// Jacobi dependence on int32 cells.
+int validate_life(Problem* pr, int ndim, const int64_t* dims, int boundary) {
+    if (ndim != 2) return set_error(TVS_E_SHAPE, "Game of Life boards are 2D");
+    int rc = validate(pr, ndim, dims, TVS_F32, TVS_BOX, 9, TVS_JACOBI, boundary);
+    if (rc) return rc;
+    pr->dtype = TVS_I32;
+    pr->rule = TVS_RULE_LIFE;
     return TVS_OK;
 }
 
@@ -245,6 +258,8 @@ Schedule default_schedule(const Problem& p) {
 int check_schedule(const Problem& p, const Schedule& s) {
     if (s.method == TVS_METHOD_PLAIN) return TVS_OK;
     if (s.k < 1) return set_error(TVS_E_INVALID, "k must be >= 1");
+    if (p.rule == TVS_RULE_LIFE && s.kern != 0)
+        return set_error(TVS_E_INVALID, "Game of Life runs on the LDS pipeline only (kern=0)");
     if (p.dependence == TVS_GAUSS_SEIDEL) {
         const int kmax = p.ndim == 1 ? 1024 : 256;
         if (s.k > kmax)

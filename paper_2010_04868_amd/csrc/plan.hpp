@@ -10,6 +10,7 @@ namespace tvs {
 const char* last_error();
 int validate(Problem* pr, int ndim, const int64_t* dims, int dtype, int shape, int order,
              int dependence, int boundary);
+int validate_life(Problem* pr, int ndim, const int64_t* dims, int boundary);
 int parse_tuning(const char* str, Schedule* s, bool* has_method);
 std::string format_tuning(const Problem& p, const Schedule& s);
 Schedule default_schedule(const Problem& p);

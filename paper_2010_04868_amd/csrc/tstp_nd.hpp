@@ -35,6 +35,11 @@
 // value and the weight is computed once per value and used by every term
 // that needs it; a product is the same rounded number wherever it is used,
 // so this changes no bit.  The result is bit-identical to the naive sweep.
+//
+// Game of Life (LIFE, 2D box on 32-bit cells) runs the same pipeline with
+// every weight one: the finished running sum is the 3 x 3 sum around the
+// point, the point's own value is the centre value its lane read one step
+// earlier, and the B2S23 rule maps the two to the new cell.
 #pragma once
 
 #include <algorithm>
@@ -105,10 +110,13 @@ __host__ __device__ inline int tile_order(int blk, const ArgsNd& a) {
 // One tile of one band.  Threads tid >= a.NT take part in the barriers only
 // (AW: the block has exactly a.NT threads).  Returns after a final LDS
 // barrier, so the caller may reuse the LDS.
-template <typename T, int D, bool BOX, bool PER, int C, int NPT, bool UNI, bool AW = false>
+template <typename T, int D, bool BOX, bool PER, int C, int NPT, bool UNI, bool AW = false,
+          bool LIFE = false>
 __device__ __forceinline__ void tstp_tile(const T* __restrict__ in, T* __restrict__ out,
                                           const ArgsNd& a, const Coeffs<T>& cf, int tile, T* lds,
                                           int tid) {
+    static_assert(!LIFE || (D == 2 && BOX && !UNI && std::is_unsigned<T>::value),
+                  "Life: 2D box neighbourhood on unsigned 32-bit arithmetic");
     using St = Stencil<D, BOX>;
     constexpr int gm_b = St::group_begin(-1), gm_e = St::group_end(-1);
     constexpr int g0_b = St::group_begin(0), g0_e = St::group_end(0);
@@ -240,7 +248,8 @@ __device__ __forceinline__ void tstp_tile(const T* __restrict__ in, T* __restric
     // Dirichlet: a fixed border point has the same value at every level, so
     // its level-j value is level j-1's value at the same point -- the centre
     // value this lane read one step earlier (stream row p-1).  Keeping those
-    // raw values avoids a global load (and its wait) in the step.
+    // raw values avoids a global load (and its wait) in the step.  Life needs
+    // the same value (the cell's own state) at every point.
     T prevc[C];
 #pragma unroll
     for (int c = 0; c < C; ++c) Acc[0][c] = Acc[1][c] = prevc[c] = T(0);
@@ -277,7 +286,7 @@ __device__ __forceinline__ void tstp_tile(const T* __restrict__ in, T* __restric
             // tile multiplies every term by its weight -- with equal weights the
             // same rounded product -- so that v keeps the raw values, which
             // are also the fixed border values of the next step (prevc).
-            constexpr bool SHARE = UNI && !BT;
+            constexpr bool SHARE = UNI && !BT && !LIFE;
             // v[r][i]: plane row ly-1+r, tile column lx-1+i (multiplied by the
             // common weight when SHARE)
             T v[R][C + 2];
@@ -309,9 +318,10 @@ __device__ __forceinline__ void tstp_tile(const T* __restrict__ in, T* __restric
                     return v[0][1 + c + St::off(q2, 1)];
             };
             // one canonical term: weight * value, or the shared product
+            // (Life: the value itself)
             auto add = [&](T acc, auto qc, int c, bool first) -> T {
                 constexpr int q2 = decltype(qc)::value;
-                const T prod = SHARE ? val(qc, c) : cf.c[q2] * val(qc, c);
+                const T prod = SHARE || LIFE ? val(qc, c) : cf.c[q2] * val(qc, c);
                 return first ? prod : acc + prod;
             };
             const int gz_out = z_org + p - 1;
@@ -330,6 +340,11 @@ __device__ __forceinline__ void tstp_tile(const T* __restrict__ in, T* __restric
                 });
                 Acc[par ^ 1][c] = m;
                 Acc[par][c] = s;
+                if constexpr (LIFE) {
+                    // B2S23: born with 2 live neighbours, survives with 2 or 3
+                    const T nbr = f - prevc[c];
+                    f = (nbr == 2u || (prevc[c] != 0u && nbr == 3u)) ? T(1) : T(0);
+                }
                 if (emit) dst[c * S] = f;
                 if constexpr (BT) {
                     // a fixed border point keeps its input value at every level:
@@ -338,8 +353,8 @@ __device__ __forceinline__ void tstp_tile(const T* __restrict__ in, T* __restric
                     const int gxc = x_org + lx + c;
                     const bool fixed = z_border || y_border || gxc == 0 || gxc == a.nx - 1;
                     if (emit && fixed) dst[c * S] = prevc[c];
-                    prevc[c] = v[MID][1 + c];
                 }
+                if constexpr (BT || LIFE) prevc[c] = v[MID][1 + c];
             }
         }
         lds_barrier();
@@ -370,12 +385,12 @@ __device__ __forceinline__ void tstp_tile(const T* __restrict__ in, T* __restric
         run(std::false_type{});
 }
 
-template <typename T, int D, bool BOX, bool PER, int C, int NPT, bool UNI>
+template <typename T, int D, bool BOX, bool PER, int C, int NPT, bool UNI, bool LIFE = false>
 __global__ __launch_bounds__(512) void tstp_nd(const T* __restrict__ in, T* __restrict__ out,
                                                ArgsNd a, Coeffs<T> cf) {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
-    tstp_tile<T, D, BOX, PER, C, NPT, UNI, true>(in, out, a, cf, tile_order(blockIdx.x, a),
-                                           reinterpret_cast<T*>(smem_raw), threadIdx.x);
+    tstp_tile<T, D, BOX, PER, C, NPT, UNI, true, LIFE>(in, out, a, cf, tile_order(blockIdx.x, a),
+                                                 reinterpret_cast<T*>(smem_raw), threadIdx.x);
 }
 
 // Paddings S (sub-row stride), Wp = C * S (row stride) and PSP (plane
@@ -442,7 +457,8 @@ inline ArgsNd make_args(const Problem& p, const BandGeom& g) {
     return a;
 }
 
-template <typename T, int D>
+// LIFE: Game of Life bands (box, periodic or Dirichlet, never uniform)
+template <typename T, int D, bool LIFE = false>
 hipError_t launch_nd_impl(const Problem& p, const BandGeom& g, const T* in, T* out,
                           const Coeffs<T>& cf, bool uniform, hipStream_t st) {
     const ArgsNd a = make_args(p, g);
@@ -461,9 +477,13 @@ hipError_t launch_nd_impl(const Problem& p, const BandGeom& g, const T* in, T* o
         hipLaunchKernelGGL(kern, grid, block, lds, st, in, out, a, cf);
         err = hipGetLastError();
     };
-#define TVS_ND(B, PR, CC, N, U) go(tstp_nd<T, D, B, PR, CC, N, U>)
-#define TVS_ND_U(B, PR, CC, N) \
-    do { if (uniform) TVS_ND(B, PR, CC, N, true); else TVS_ND(B, PR, CC, N, false); } while (0)
+#define TVS_ND(B, PR, CC, N, U) go(tstp_nd<T, D, B, PR, CC, N, U, LIFE>)
+#define TVS_ND_U(B, PR, CC, N)                                         \
+    do {                                                               \
+        if constexpr (LIFE) TVS_ND(B, PR, CC, N, false);               \
+        else if (uniform) TVS_ND(B, PR, CC, N, true);                  \
+        else TVS_ND(B, PR, CC, N, false);                              \
+    } while (0)
 #define TVS_ND_N(B, PR, CC)                               \
     do {                                                  \
         if (npt <= 1) TVS_ND_U(B, PR, CC, 1);             \
@@ -478,7 +498,10 @@ hipError_t launch_nd_impl(const Problem& p, const BandGeom& g, const T* in, T* o
         case 16: TVS_ND_N(B, PR, 16); break; \
         default: return hipErrorInvalidValue; \
     }
-    if (box) {
+    if constexpr (LIFE) {
+        if (!box) return hipErrorInvalidValue;
+        if (per) { TVS_ND_C(true, true) } else { TVS_ND_C(true, false) }
+    } else if (box) {
         if (per) { TVS_ND_C(true, true) } else { TVS_ND_C(true, false) }
     } else {
         if (per) { TVS_ND_C(false, true) } else { TVS_ND_C(false, false) }
@@ -505,5 +528,7 @@ hipError_t launch_nd_f32_2d(const Problem&, const BandGeom&, const float*, float
                             const Coeffs<float>&, bool, hipStream_t);
 hipError_t launch_nd_f32_3d(const Problem&, const BandGeom&, const float*, float*,
                             const Coeffs<float>&, bool, hipStream_t);
+hipError_t launch_nd_life_2d(const Problem&, const BandGeom&, const uint32_t*, uint32_t*,
+                             hipStream_t);
 
 }  // namespace tvs

@@ -31,7 +31,8 @@ std::string problem_key(const Problem& p) {
     std::ostringstream o;
     o << "nd" << p.ndim << ":";
     for (int a = 0; a < p.ndim; ++a) o << (a ? "x" : "") << p.dims[a];
-    o << ":" << (p.dtype == TVS_F64 ? "f64" : "f32") << ":" << (p.shape == TVS_BOX ? "box" : "star")
+    o << ":" << (p.rule == TVS_RULE_LIFE ? "life" : p.dtype == TVS_F64 ? "f64" : "f32") << ":"
+      << (p.shape == TVS_BOX ? "box" : "star")
       << p.order << ":" << (p.dependence == TVS_JACOBI ? "jacobi" : "gs") << ":"
       << (p.boundary == TVS_PERIODIC ? "periodic" : "dirichlet");
     return o.str();
@@ -182,7 +183,10 @@ using namespace tvs;
 extern "C" int stencil_tune(tvs_plan* p, void* grid, const double* coeffs, int64_t T_probe,
                             void* stream, char* best, size_t best_len) {
     clear_error();
-    if (!p || !grid || !coeffs) return set_error(TVS_E_INVALID, "NULL argument");
+    if (!p || !grid) return set_error(TVS_E_INVALID, "NULL argument");
+    static const double kNoWeights[kMaxPoints] = {};
+    if (p->prob.rule == TVS_RULE_LIFE) coeffs = kNoWeights;  // the rule has no weights
+    if (!coeffs) return set_error(TVS_E_INVALID, "NULL argument");
     if (T_probe < 1) return set_error(TVS_E_INVALID, "T_probe must be >= 1");
     hipStream_t st = (hipStream_t)stream;
     const Problem& pr = p->prob;

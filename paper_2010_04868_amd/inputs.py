@@ -14,6 +14,8 @@ never written.
 Generator: numpy ``Generator(PCG64(seed))``.  FP64 problems draw float64
 values, FP32 problems draw float32 values (the FP64 oracle then runs on those
 same values widened, so that a comparison measures arithmetic error only).
+Game of Life boards (int32 cells) draw each cell live (1) with probability
+``density`` from the same generator.
 """
 from __future__ import annotations
 
@@ -26,9 +28,9 @@ import numpy as np
 STAR, BOX = 0, 1
 JACOBI, GAUSS_SEIDEL = 0, 1
 DIRICHLET, PERIODIC = 0, 1
-F32, F64 = 0, 1
+F32, F64, I32 = 0, 1, 2
 
-_NP = {F32: np.float32, F64: np.float64}
+_NP = {F32: np.float32, F64: np.float64, I32: np.int32}
 
 
 def np_dtype(dtype: int):
@@ -95,7 +97,23 @@ def uniform_grid(dims: Sequence[int], dtype: int, seed, zero_border: bool = Fals
     return a
 
 
+def life_board(dims: Sequence[int], seed, density: float = 0.5,
+               zero_border: bool = False) -> np.ndarray:
+    """int32 0/1 board: each cell live with probability ``density`` (PCG64(seed)).
+
+    With ``zero_border`` the outer layer is dead.
+    """
+    rng = np.random.Generator(np.random.PCG64(seed))
+    a = (rng.random(tuple(int(n) for n in dims)) < density).astype(np.int32)
+    if zero_border:
+        a[0, :] = a[-1, :] = 0
+        a[:, 0] = a[:, -1] = 0
+    return a
+
+
 def make_grid(p: Problem) -> np.ndarray:
+    if p.dtype == I32:
+        return life_board(p.dims, p.seed, 0.5, p.zero_border)
     return uniform_grid(p.dims, p.dtype, p.seed, p.zero_border)
 
 
@@ -143,11 +161,19 @@ def gs2d5p(n: int = 4096, T: int = 100) -> Problem:
                    tuple([0.2] * 5), T, 4, zero_border=True)
 
 
+def life2d(n: int = 8000, T: int = 2000) -> Problem:
+    """Game of Life B2S23 on an n x n int32 board (the paper's Life workload,
+    8000^2 cells over 2000 steps in Table 1): cells live with probability 1/2,
+    dead fixed border.  The rule has no weights."""
+    return Problem("life2d", (n, n), I32, BOX, 9, JACOBI, DIRICHLET, (), T, 8, zero_border=True)
+
+
 WORKLOADS = {
     "heat1d_3p": heat1d,
     "box2d9p": box2d9p,
     "star3d7p": star3d7p,
     "gs2d5p": gs2d5p,
+    "life2d": life2d,
 }
 
 

@@ -104,6 +104,37 @@ def test_huge_plane_runs_plain():
                                     tuning="method=tstp,k=2,w=64,h=32,c=8")) == E["TVS_E_INVALID"]
 
 
+def test_life_plans_without_device():
+    lib = _lib.load()
+    p = tvs.LifePlan((64, 80), DIRICHLET)
+    inf = p.info()
+    assert inf["rule"] == tvs.RULE_LIFE and inf["dtype"] == tvs.I32
+    assert (inf["shape"], inf["order"], inf["dependence"]) == (BOX, 9, JACOBI)
+    assert inf["kern"] == 0 and inf["method"] == 1
+    assert tvs.Plan((64, 64), F64, BOX, 9).info()["rule"] == tvs.RULE_WEIGHTED
+    q = tvs.LifePlan((64, 80), PERIODIC, "method=plain")
+    assert q.info()["method"] == 0 and q.info()["boundary"] == PERIODIC
+    r = tvs.LifePlan((64, 80), DIRICHLET, inf["tuning"])
+    assert r.info()["tuning"] == inf["tuning"]
+    # 2D only; the register pipeline and weighted int32 grids do not exist
+    assert code_of(lambda: tvs.LifePlan((8, 8, 8))) == E["TVS_E_SHAPE"]
+    assert code_of(lambda: tvs.LifePlan((2, 8))) == E["TVS_E_SHAPE"]
+    assert code_of(lambda: tvs.LifePlan((8, 8), 3)) == E["TVS_E_INVALID"]
+    assert code_of(lambda: tvs.LifePlan((64, 64), DIRICHLET, "method=tstp,kern=1,k=8,c=4")) \
+        == E["TVS_E_INVALID"]
+    assert code_of(lambda: tvs.Plan((8, 8), tvs.I32, BOX, 9)) == E["TVS_E_INVALID"]
+    fake = ctypes.c_void_p(0x1000)
+    # Life: coeffs NULL is accepted (T = 0 enqueues nothing); weighted plans need them
+    assert lib.stencil_run(p.handle, fake, None, 0, None) == 0
+    w = tvs.Plan((16, 16), F64, STAR, 5)
+    assert lib.stencil_run(w.handle, fake, None, 3, None) == E["TVS_E_INVALID"]
+    P = (ctypes.c_void_p * 1)(p.handle.value)
+    G = (ctypes.c_void_p * 1)(0x1000)
+    C = (ctypes.POINTER(ctypes.c_double) * 1)()
+    Tn = (ctypes.c_int64 * 1)(3)
+    assert lib.stencil_batch_run(1, P, G, C, Tn, None) == E["TVS_E_UNSUPPORTED"]
+
+
 def test_run_argument_errors_without_device():
     lib = _lib.load()
     p = tvs.Plan((16, 16), F64, STAR, 5)

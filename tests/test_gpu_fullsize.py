@@ -14,9 +14,10 @@ import concurrent.futures as cf
 import numpy as np
 import pytest
 
+import oracle
 from helpers import assert_bitwise, max_rel_err, oracle_sweep
 from paper_2010_04868_amd import inputs
-from paper_2010_04868_amd.inputs import DIRICHLET, F32, F64, PERIODIC
+from paper_2010_04868_amd.inputs import DIRICHLET, F32, F64, I32, PERIODIC
 
 pytestmark = pytest.mark.gpu
 
@@ -51,8 +52,11 @@ def window_check(p, u0, got, lo, size, prec_arr=None):
             win = np.take(win, np.arange(a0, a1) % p.dims[a], axis=a)
     else:
         win = u0[tuple(slice(a0, a1) for a0, a1 in sl_in)]
-    ref = oracle_sweep(np.ascontiguousarray(win), p.coeffs, p.shape, p.order, p.dependence,
-                       DIRICHLET, T)
+    if p.dtype == I32:
+        ref = oracle.life(np.ascontiguousarray(win), DIRICHLET, T)
+    else:
+        ref = oracle_sweep(np.ascontiguousarray(win), p.coeffs, p.shape, p.order, p.dependence,
+                           DIRICHLET, T)
     inner_ref = ref[tuple(slice(b0, b1) for b0, b1 in sl_out)]
     inner_got = got[tuple(slice(l, l + size) for l in lo)]
     return inner_got, inner_ref
@@ -99,6 +103,20 @@ def test_star3d7p_full_size_windows():
         los = ((0, 0, 0), (300, 17, 511 - 12))
         for lo, (g, r) in parallel_windows(p, u0, got, los, 12).items():
             assert_bitwise(g, r, f"3D {p.name} window at {lo}")
+
+
+def test_life2d_full_size_windows():
+    # the 8000^2 board in the benchmark's schedule; 200 generations keep the
+    # oracle's windows small (each output depends on the board within 200 cells)
+    p = inputs.life2d(T=200)
+    u0 = inputs.make_grid(p)
+    got = run_gpu(p, u0)
+    assert set(np.unique(got)) <= {0, 1}
+    n = p.dims[0]
+    los = ((0, 0), (0, n - 48), (n - 48, 0), (n - 48, n - 48), (n // 2 - 24, n // 3),
+           (1234, 5678))
+    for lo, (g, r) in parallel_windows(p, u0, got, los, 48).items():
+        assert_bitwise(g, r, f"Life window at {lo}")
 
 
 def test_gs2d5p_full_size_exact():
