@@ -36,33 +36,41 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 ALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 ALU_PEAK_TOPS_F32 = 2 * ALU_PEAK_TOPS
 METRIC = "GStencil/s + % HBM roofline vs plain sweep; p50/p99 latency mixed load"
-PROFILE = os.path.join(ROOT, "profiles", "tstp_nd_box2d9p_8192_f64.md")
-KERNEL_SOURCES = ["tstp_nd.hpp", "tstp_nd_f64_2d.hip", "jacobi_tstp.hip", "common.hpp",
-                  "kernels.hpp"]
+# workload -> (rocprof summary of its band kernel, the sources that kernel is built from)
+PROFILES = {
+    "box2d9p": ("tstp_nd_box2d9p_8192_f64.md",
+                ["tstp_nd.hpp", "tstp_nd_f64_2d.hip", "jacobi_tstp.hip", "common.hpp",
+                 "kernels.hpp"]),
+    "life2d": ("tstp_nd_life2d_8000_i32.md",
+               ["tstp_nd.hpp", "tstp_nd_life_2d.hip", "jacobi_tstp.hip", "common.hpp",
+                "kernels.hpp"]),
+}
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def kernel_hash() -> str:
+def kernel_hash(workload: str = "box2d9p") -> str:
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
+    for f in PROFILES[workload][1]:
         with open(os.path.join(ROOT, "paper_2010_04868_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def profiled_traffic():
+def profiled_traffic(workload: str):
     """HBM bytes per band launch from the committed rocprof summary, if it was
     taken on the current kernel sources (else None)."""
+    if workload not in PROFILES:
+        return None
     try:
-        text = open(PROFILE).read()
+        text = open(os.path.join(ROOT, "profiles", PROFILES[workload][0])).read()
     except OSError:
         return None
     m = re.search(r"kernel sources hash: `([0-9a-f]+)`", text)
     t = re.search(r"HBM traffic per band launch \(bytes\): `([0-9.eE+]+)`", text)
-    if not m or not t or m.group(1) != kernel_hash():
+    if not m or not t or m.group(1) != kernel_hash(workload):
         return None
     return float(t.group(1))
 
@@ -369,7 +377,7 @@ def main():
 
     # int32 has no packed two-wide adds: the unpacked rate, as for FP64
     peak = ALU_PEAK_TOPS if eb == 8 or life else ALU_PEAK_TOPS_F32
-    traffic = profiled_traffic() if args.workload == "box2d9p" and args.n is None else None
+    traffic = profiled_traffic(args.workload) if args.n is None and args.T is None else None
     out = {
         "metric": METRIC,
         "value": round(value, 2),
