@@ -45,6 +45,9 @@ def _load():
     lib.oracle_life.argtypes = [ctypes.c_int64, ctypes.c_int64, ctypes.c_int, ctypes.c_int64,
                                 ctypes.POINTER(ctypes.c_int32)]
     lib.oracle_life.restype = ctypes.c_int
+    u8p, i32p = ctypes.POINTER(ctypes.c_uint8), ctypes.POINTER(ctypes.c_int32)
+    lib.oracle_lcs.argtypes = [u8p, ctypes.c_int64, u8p, ctypes.c_int64, i32p, i32p]
+    lib.oracle_lcs.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -110,3 +113,27 @@ def life(u: np.ndarray, boundary: int, T: int) -> np.ndarray:
     if rc != 0:
         raise OracleError(f"oracle life failed ({rc})")
     return g
+
+
+def lcs(a, b, row=None, col=None):
+    """Longest-common-subsequence table of byte sequences a (m) and b (n), as
+    the 1D Gauss-Seidel-like dynamic program of Section 3.4: from the boundary
+    row lcs[0][0..n] (default zeros) and column lcs[1..m][0] (``col[1:]``,
+    default zeros) to ``(last_row, last_col)`` = (lcs[m][0..n], lcs[0..m][n]).
+    With zero boundaries ``last_row[-1]`` is the LCS length.  Inputs are not
+    modified.
+    """
+    lib = _load()
+    a = np.ascontiguousarray(a, dtype=np.uint8)
+    b = np.ascontiguousarray(b, dtype=np.uint8)
+    m, n = a.size, b.size
+    r = np.zeros(n + 1, np.int32) if row is None else np.array(row, dtype=np.int32, copy=True)
+    c = np.zeros(m + 1, np.int32) if col is None else np.array(col, dtype=np.int32, copy=True)
+    if r.shape != (n + 1,) or c.shape != (m + 1,):
+        raise OracleError("row must hold n+1 values and col m+1")
+    u8p, i32p = ctypes.POINTER(ctypes.c_uint8), ctypes.POINTER(ctypes.c_int32)
+    rc = lib.oracle_lcs(a.ctypes.data_as(u8p), m, b.ctypes.data_as(u8p), n,
+                        r.ctypes.data_as(i32p), c.ctypes.data_as(i32p))
+    if rc != 0:
+        raise OracleError(f"oracle lcs failed ({rc})")
+    return r, c

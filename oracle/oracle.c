@@ -45,7 +45,10 @@
  * convergence factors of the discrete Laplacian.  The Game of Life sweep
  * (below) is pinned by boards whose next state is derived by counting
  * neighbours by hand, and by its invariants (fixed border, the square's
- * symmetries, translation on the torus, composition).
+ * symmetries, translation on the torus, composition).  The LCS table is
+ * pinned by brute force over all subsequences of short strings, a textbook
+ * example, symmetry, and the chaining of rectangles through the wavefront
+ * arrays.
  */
 #include <stddef.h>
 #include <stdint.h>
@@ -246,5 +249,53 @@ int oracle_life(int64_t n0, int64_t n1, int boundary, int64_t T, int32_t *u)
     }
     if (cur != u) memcpy(u, cur, (size_t)n * sizeof(int32_t));
     free(v);
+    return 0;
+}
+
+/*
+ * Longest common subsequence (Section 3.4, "Longest common subsequence"):
+ * the dynamic program over the iteration space x = 1..m (time), y = 1..n
+ * (space), where lcs[x][y] is the length of a longest common subsequence of
+ * the prefixes a[1..x] and b[1..y]:
+ *   lcs[x][y] = lcs[x-1][y-1] + 1              if a[x] == b[y],
+ *             = max(lcs[x-1][y], lcs[x][y-1])  otherwise.
+ * The run starts from a boundary row lcs[0][0..n] (row, n+1 values) and a
+ * boundary column lcs[1..m][0] (col[1..m]; col[0] is not read), and returns
+ * the last row lcs[m][0..n] in row and the last column lcs[0..m][n] in col:
+ * the two wavefront arrays through which rectangles of the iteration space
+ * are chained.  With all-zero boundaries, lcs[m][n] is the LCS length.
+ * Sequences are byte strings; a[1..m] is a[0..m-1] in memory.  Row by row,
+ * one row of storage.  Returns 0, -1 on a bad argument, -5 out of memory.
+ */
+int oracle_lcs(const uint8_t *a, int64_t m, const uint8_t *b, int64_t n, int32_t *row,
+               int32_t *col)
+{
+    if (m < 0 || n < 0 || !row || !col || (m > 0 && !a) || (n > 0 && !b)) return -1;
+    int32_t *prev = (int32_t *)malloc((size_t)(n + 1) * sizeof(int32_t));
+    int32_t *cur = (int32_t *)malloc((size_t)(n + 1) * sizeof(int32_t));
+    if (!prev || !cur) {
+        free(prev);
+        free(cur);
+        return -5;
+    }
+    memcpy(prev, row, (size_t)(n + 1) * sizeof(int32_t));
+    col[0] = prev[n];  /* lcs[0][n] */
+    for (int64_t x = 1; x <= m; ++x) {
+        cur[0] = col[x];  /* lcs[x][0], the boundary column */
+        for (int64_t y = 1; y <= n; ++y) {
+            if (a[x - 1] == b[y - 1]) {
+                cur[y] = prev[y - 1] + 1;
+            } else {
+                cur[y] = prev[y] > cur[y - 1] ? prev[y] : cur[y - 1];
+            }
+        }
+        col[x] = cur[n];
+        int32_t *tmp = prev;
+        prev = cur;
+        cur = tmp;
+    }
+    memcpy(row, prev, (size_t)(n + 1) * sizeof(int32_t));
+    free(prev);
+    free(cur);
     return 0;
 }

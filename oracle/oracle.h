@@ -13,6 +13,10 @@
 /* Canonical offsets (lexicographic, axis 0 most significant) as npoints rows
  * of ndim ints.  Returns the number of points, or a negative error code. */
 int oracle_offsets(int ndim, int shape, int npoints, int *offsets_out);
+/* Longest common subsequence table from a boundary row (n+1) and column
+ * (col[1..m]) to the last row and column (0 = ok); see oracle.c. */
+int oracle_lcs(const uint8_t *a, int64_t m, const uint8_t *b, int64_t n, int32_t *row,
+               int32_t *col);
 /* Game of Life B2S23 on an n0 x n1 int32 board, T steps in place (0 = ok). */
 int oracle_life(int64_t n0, int64_t n1, int boundary, int64_t T, int32_t *u);
 

@@ -168,6 +168,34 @@ def life2d(n: int = 8000, T: int = 2000) -> Problem:
     return Problem("life2d", (n, n), I32, BOX, 9, JACOBI, DIRICHLET, (), T, 8, zero_border=True)
 
 
+@dataclasses.dataclass
+class LcsProblem:
+    """Longest common subsequence of two random byte sequences (Section 3.4)."""
+
+    name: str
+    m: int
+    n: int
+    alphabet: int
+    seed: int
+
+    def cells(self) -> int:
+        return self.m * self.n
+
+
+def lcs_sequences(m: int, n: int, seed, alphabet: int = 4) -> Tuple[np.ndarray, np.ndarray]:
+    """Two uint8 sequences of lengths m and n, letters uniform over
+    0..alphabet-1, drawn from PCG64(seed) (the first sequence first)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    a = rng.integers(0, alphabet, size=int(m), dtype=np.uint8)
+    b = rng.integers(0, alphabet, size=int(n), dtype=np.uint8)
+    return a, b
+
+
+def lcs200k(m: int = 200000, n: int = 200000) -> LcsProblem:
+    """The paper's LCS size (Table 1: 200000 x 200000), a 4-letter alphabet."""
+    return LcsProblem("lcs", m, n, 4, 9)
+
+
 WORKLOADS = {
     "heat1d_3p": heat1d,
     "box2d9p": box2d9p,

@@ -504,3 +504,95 @@ def test_life_periodic_translation_and_composition():
     assert np.array_equal(oracle.life(shifted, PERIODIC, 7),
                           np.roll(np.roll(got, 5, axis=0), -3, axis=1))
     assert np.array_equal(oracle.life(oracle.life(u, PERIODIC, 3), PERIODIC, 4), got)
+
+
+# Longest common subsequence (Section 3.4, "Longest common subsequence"): the
+# dynamic program's table is pinned by the definition of a longest common
+# subsequence itself (brute force over subsequences), a textbook example,
+# symmetry, and the chaining of rectangles through the wavefront arrays.
+def _is_subsequence(s, t):
+    it = iter(t)
+    return all(any(c == d for d in it) for c in s)
+
+
+def _lcs_brute(a, b):
+    best = 0
+    for mask in range(1 << len(a)):
+        sub = [a[i] for i in range(len(a)) if mask >> i & 1]
+        if len(sub) > best and _is_subsequence(sub, b):
+            best = len(sub)
+    return best
+
+
+def test_lcs_brute_force_all_prefixes():
+    rng = np.random.default_rng(21)
+    for trial in range(40):
+        m, n = int(rng.integers(0, 8)), int(rng.integers(0, 8))
+        k = int(rng.integers(1, 4))
+        a = rng.integers(0, k, m).astype(np.uint8)
+        b = rng.integers(0, k, n).astype(np.uint8)
+        row, col = oracle.lcs(a, b)
+        # last row: prefixes of b; last column: prefixes of a
+        assert [int(v) for v in row] == [_lcs_brute(list(a), list(b[:y])) for y in range(n + 1)]
+        assert [int(v) for v in col] == [_lcs_brute(list(a[:x]), list(b)) for x in range(m + 1)]
+
+
+def test_lcs_textbook_and_special_cases():
+    a = np.frombuffer(b"ABCBDAB", np.uint8)
+    b = np.frombuffer(b"BDCABA", np.uint8)
+    assert oracle.lcs(a, b)[0][-1] == 4      # e.g. "BCBA"
+    s = np.random.default_rng(3).integers(0, 4, 500).astype(np.uint8)
+    assert oracle.lcs(s, s)[0][-1] == 500    # identical strings
+    assert oracle.lcs(s, s + 4)[0][-1] == 0  # disjoint alphabets
+    r, c = oracle.lcs(s, np.zeros(0, np.uint8))
+    assert r.tolist() == [0] and c.tolist() == [0] * 501
+    r, c = oracle.lcs(np.zeros(0, np.uint8), s)
+    assert r.tolist() == [0] * 501 and c.tolist() == [0]
+
+
+def test_lcs_symmetry_and_unit_steps():
+    rng = np.random.default_rng(5)
+    a = rng.integers(0, 4, 300).astype(np.uint8)
+    b = rng.integers(0, 4, 410).astype(np.uint8)
+    r_ab, c_ab = oracle.lcs(a, b)
+    r_ba, c_ba = oracle.lcs(b, a)
+    assert r_ab[-1] == r_ba[-1]
+    # transposing the table swaps the last row and the last column
+    assert np.array_equal(r_ab, c_ba) and np.array_equal(c_ab, r_ba)
+    for v in (r_ab, c_ab):
+        assert set(np.diff(v).tolist()) <= {0, 1}
+
+
+def test_lcs_rectangles_chain_through_wavefront_arrays():
+    rng = np.random.default_rng(8)
+    a = rng.integers(0, 3, 257).astype(np.uint8)
+    b = rng.integers(0, 3, 333).astype(np.uint8)
+    row, col = oracle.lcs(a, b)
+    # split b: the right rectangle starts from the left one's last column
+    n1 = 150
+    r1, c1 = oracle.lcs(a, b[:n1])
+    r2, c2 = oracle.lcs(a, b[n1:], row=np.zeros(b.size - n1 + 1, np.int32), col=c1)
+    assert np.array_equal(np.concatenate([r1, r2[1:]]), row)
+    assert np.array_equal(c2[1:], col[1:])
+    # split a: the lower rectangle starts from the upper one's last row
+    m1 = 100
+    r1, c1 = oracle.lcs(a[:m1], b)
+    r2, c2 = oracle.lcs(a[m1:], b, row=r1, col=np.zeros(a.size - m1 + 1, np.int32))
+    assert np.array_equal(r2, row)
+    assert np.array_equal(np.concatenate([c1, c2[1:]]), col)
+    # a 3 x 4 grid of rectangles, in anti-diagonal order, equals the whole
+    xs, ys = [0, 90, 200, 257], [0, 60, 61, 250, 333]
+    rows = {j: np.zeros(ys[j + 1] - ys[j] + 1, np.int32) for j in range(4)}
+    cols = {i: np.zeros(xs[i + 1] - xs[i] + 1, np.int32) for i in range(3)}
+    for d in range(6):
+        for i in range(3):
+            j = d - i
+            if not 0 <= j < 4:
+                continue
+            # a rectangle's last row starts with its corner (the boundary
+            # column's last value): it is the next rectangle's whole top row
+            r, c = oracle.lcs(a[xs[i]:xs[i + 1]], b[ys[j]:ys[j + 1]], row=rows[j], col=cols[i])
+            rows[j], cols[i] = r, c
+    assert np.array_equal(np.concatenate([rows[0]] + [rows[j][1:] for j in range(1, 4)]), row)
+    assert np.array_equal(np.concatenate([cols[0]] + [cols[i][1:] for i in range(1, 3)])[1:],
+                          col[1:])
