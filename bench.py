@@ -87,7 +87,13 @@ WORKLOADS = {
     "gs2d5p": (lambda inp, n, T: inp.gs2d5p(**_kw(n, T)), "2D 5-point Gauss-Seidel FP64"),
     "gs1d3p": (lambda inp, n, T: inp.gs1d3p(**_kw(n, T)), "1D 3-point Gauss-Seidel FP64"),
     "life2d": (lambda inp, n, T: inp.life2d(**_kw(n, T)), "Game of Life B2S23, int32 cells"),
+    "lcs": (None, "longest common subsequence, 200000 x 200000"),
 }
+
+# Integer operations of one LCS cell in the branch-free form of the
+# recurrence: the letter comparison, the diagonal +1, the max of north and
+# west, and the select between the two.
+LCS_OPS = 4
 
 # Integer operations of one Life update by its definition: 7 additions for
 # the sum of 8 neighbours, and the rule (two equality tests, a non-zero test,
@@ -287,6 +293,75 @@ def batch_measure(torch, tvs, inputs, n_grids=48, seed=7, reps=3):
     }
 
 
+def lcs_bench(torch, tvs, inputs, args, copy_gbs):
+    """LCS of two random 4-letter sequences, Table 1's size unless --n is given
+    (then n x n).  A step is one whole table from zero boundaries."""
+    p = inputs.lcs200k() if args.n is None else inputs.lcs200k(args.n, args.n)
+    a, b = inputs.lcs_sequences(p.m, p.n, p.seed, p.alphabet)
+    da, db = torch.from_numpy(a).to("cuda"), torch.from_numpy(b).to("cuda")
+    row = torch.zeros(p.n + 1, dtype=torch.int32, device="cuda")
+    col = torch.zeros(p.m + 1, dtype=torch.int32, device="cuda")
+    plan = tvs.LcsPlan(p.m, p.n, args.tuning)
+    tw, tr = plan.tile_width, plan.tile_rows
+
+    def solve():
+        row.zero_()
+        col.zero_()
+        plan.run(da, db, row, col)
+
+    for _ in range(1 + args.warmup):
+        solve()
+    torch.cuda.synchronize()
+    ms = time_runs(torch, solve, args.steps)
+    cells = p.m * p.n
+    value = cells / (ms / 1e3) / 1e9
+    launches = (p.m + tr - 1) // tr + (p.n + tw - 1) // tw - 1
+    kernel_ms = ms / launches                  # average tile launch (init and zeroing included)
+    ops = cells * LCS_OPS / launches
+    achieved = ops / (kernel_ms / 1e3) / 1e12
+    log(f"lcs: w={tw} r={tr} {ms:.2f} ms/solve, {value:.1f} GCells/s, {launches} launches, "
+        f"{kernel_ms * 1e3:.2f} us per launch, LCS length {int(row[-1].item())}")
+    out = {
+        "metric": METRIC,
+        "value": round(value, 2),
+        "unit": "GCells/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "i32",
+        "data": f"synthetic: two uniform 4-letter sequences, PCG64(seed {p.seed})",
+        "config": {"workload": f"longest common subsequence {p.m} x {p.n}, 4-letter alphabet, "
+                               "zero boundaries", "schedule": f"w={tw},r={tr}", "cells": cells,
+                   "lcs_length": int(row[-1].item())},
+        "copy_GBs": round(copy_gbs, 1),
+        "roofline": {"bound": "alu", "achieved": round(achieved, 3),
+                     "peak": round(ALU_PEAK_TOPS, 2), "unit": "TOP/s (int32)",
+                     "frac": round(achieved / ALU_PEAK_TOPS, 4), "traffic": None,
+                     "kernel": f"lcs_diag (one launch per anti-diagonal of {tr} x {tw} tiles)",
+                     "kernel_ms": round(kernel_ms, 5),
+                     "algorithmic_bytes": p.m + p.n + 8 * (p.m + p.n)},
+    }
+    if not args.no_cpu:
+        import oracle
+        rows = 64
+        t0 = time.perf_counter()
+        oracle.lcs(a[:rows], b)
+        one = time.perf_counter() - t0
+        rows = max(64, min(p.m, int(64 * 15.0 / max(one, 1e-6))))
+        t0 = time.perf_counter()
+        oracle.lcs(a[:rows], b)
+        dt = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": round(rows * p.n / dt / 1e9, 4), "unit": "GCells/s",
+                               "cores": 1, "kind": "oracle",
+                               "sample": f"the first {rows} rows of the table ({rows} x {p.n}), "
+                                         f"single thread, {dt:.1f} s"}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -325,6 +400,9 @@ def main():
     log(f"copy 1 GiB: {copy_ms:.3f} ms = {copy_gbs:.0f} GB/s (read + write)")
     del src, dst
 
+    if args.workload == "lcs":
+        print(json.dumps(lcs_bench(torch, tvs, inputs, args, copy_gbs)), flush=True)
+        return
     p = WORKLOADS[args.workload][0](inputs, args.n, args.T)
     u0 = inputs.make_grid(p)
     grid = torch.from_numpy(u0).to("cuda")

@@ -201,6 +201,48 @@ int stencil_batch_run(int n, tvs_plan *const *plans, void *const *grids,
 int stencil_tune(tvs_plan *plan, void *grid, const double *coeffs, int64_t T_probe,
                  void *stream, char *best, size_t best_len);
 
+/* ---- longest common subsequence ------------------------------------------ */
+/*
+ * The LCS dynamic program as a 1D Gauss-Seidel-like stencil (Section 3.4,
+ * "Longest common subsequence"): with x = 1..m as the time axis and
+ * y = 1..n as the space axis,
+ *   L[x][y] = L[x-1][y-1] + 1            if A[x] == B[y],
+ *           = max(L[x-1][y], L[x][y-1])  otherwise,
+ * where A[x] = a[x-1] and B[y] = b[y-1] are bytes.  A run starts from a
+ * boundary row L[0][0..n] and a boundary column L[1..m][0] and returns the
+ * last row L[m][0..n] and the last column L[0..m][n]: the wavefront arrays
+ * through which rectangles of the iteration space are chained.  With zero
+ * boundaries, L[m][n] is the length of a longest common subsequence of A and
+ * B (and L[m][y], L[x][n] those of A and B[1..y], A[1..x] and B).
+ */
+typedef struct tvs_lcs tvs_lcs;
+
+/* Plan a run for lengths m, n (each 0 .. 2^31-256).  tuning: NULL, or
+ * comma-separated "w=W" (tile width in columns, a multiple of 64 in 64..4096,
+ * default 512) and "r=R" (tile height in rows, a multiple of 64 in 64..1024,
+ * default 256: one wave per 64 rows); (R/64 + 1) x (W + 192) int32 values
+ * must fit 160 KiB of LDS.  No device call; a corner array of ceil(n/W)
+ * int32 values is allocated at the first run. */
+int stencil_lcs_plan(tvs_lcs **out, int64_t m, int64_t n, const char *tuning);
+/* The plan's tile width in columns and height in rows (TVS_E_INVALID for NULL). */
+int stencil_lcs_tile_width(const tvs_lcs *plan);
+int stencil_lcs_tile_rows(const tvs_lcs *plan);
+/*
+ * Enqueue the run on stream (NULL = the null stream).
+ *   a    device, m bytes (may be NULL when m = 0)
+ *   b    device, n bytes (may be NULL when n = 0)
+ *   row  device int32[n+1]: in L[0][y]; out L[m][y], y = 0..n
+ *   col  device int32[m+1]: in col[x] = L[x][0] for x = 1..m (col[0] is not
+ *        read); out col[x] = L[x][n], x = 0..m
+ * Values are int32; every L is the sum of a boundary value and at most
+ * min(m, n), which must not overflow.  a, b, row and col must not overlap.
+ * One plan runs on one stream at a time.
+ */
+int stencil_lcs_run(tvs_lcs *plan, const uint8_t *a, const uint8_t *b, int32_t *row,
+                    int32_t *col, void *stream);
+/* Free the plan (waits for the device first).  NULL is a no-op. */
+int stencil_lcs_destroy(tvs_lcs *plan);
+
 /* ---- serving: continuous batching of stencil solves ----------------------- */
 typedef struct tvs_server tvs_server;
 

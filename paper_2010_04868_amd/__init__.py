@@ -18,7 +18,7 @@ from .inputs import (BOX, DIRICHLET, F32, F64, GAUSS_SEIDEL, I32, JACOBI, PERIOD
 METHOD_PLAIN, METHOD_TSTP = 0, 1
 RULE_WEIGHTED, RULE_LIFE = 0, 1
 
-__all__ = ["Plan", "LifePlan", "run", "run_simple", "batch_run", "Server", "StencilError",
+__all__ = ["Plan", "LifePlan", "LcsPlan", "run", "run_simple", "batch_run", "Server", "StencilError",
            "load", "STAR", "BOX", "JACOBI", "GAUSS_SEIDEL", "DIRICHLET", "PERIODIC", "F32", "F64",
            "I32", "METHOD_PLAIN", "METHOD_TSTP", "RULE_WEIGHTED", "RULE_LIFE", "version"]
 
@@ -146,6 +146,52 @@ class LifePlan(Plan):
 
     def tune(self, grid, coeffs=None, T_probe: int = 1, stream=None) -> str:
         return super().tune(grid, None, T_probe, stream)
+
+
+class LcsPlan:
+    """Longest common subsequence of byte sequences of lengths m and n
+    (``stencil_lcs_plan``): the 1D Gauss-Seidel-like dynamic program of
+    Section 3.4 on device tensors."""
+
+    def __init__(self, m: int, n: int, tuning: Optional[str] = None):
+        self._h = ctypes.c_void_p()
+        check(load().stencil_lcs_plan(ctypes.byref(self._h), int(m), int(n),
+                                      tuning.encode() if tuning else None))
+        self.m, self.n = int(m), int(n)
+
+    @property
+    def tile_width(self) -> int:
+        return load().stencil_lcs_tile_width(self._h)
+
+    @property
+    def tile_rows(self) -> int:
+        return load().stencil_lcs_tile_rows(self._h)
+
+    def run(self, a, b, row, col, stream=None) -> None:
+        """From the boundary row (int32, n+1) and column (int32, m+1; entry 0
+        unused) to the last row and column, in place, asynchronously."""
+        torch = _torch()
+        for t, dt, size in ((a, torch.uint8, self.m), (b, torch.uint8, self.n),
+                            (row, torch.int32, self.n + 1), (col, torch.int32, self.m + 1)):
+            if t.dtype != dt or t.numel() != size or not t.is_cuda or not t.is_contiguous():
+                raise ValueError("a, b: contiguous uint8 device tensors of m and n elements; "
+                                 "row, col: contiguous int32 device tensors of n+1 and m+1")
+        check(load().stencil_lcs_run(self._h, ctypes.c_void_p(a.data_ptr()),
+                                     ctypes.c_void_p(b.data_ptr()),
+                                     ctypes.c_void_p(row.data_ptr()),
+                                     ctypes.c_void_p(col.data_ptr()),
+                                     ctypes.c_void_p(_stream_handle(stream))))
+
+    def close(self) -> None:
+        if self._h:
+            load().stencil_lcs_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def run(problem: Problem, grid, T: Optional[int] = None, tuning: Optional[str] = None,

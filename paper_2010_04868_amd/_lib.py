@@ -80,6 +80,11 @@ SIGNATURES = [
     ("stencil_server_stats", ctypes.c_int, [vp, ctypes.POINTER(ServerStats)]),
     ("stencil_server_now", ctypes.c_double, [vp]),
     ("stencil_server_destroy", ctypes.c_int, [vp]),
+    ("stencil_lcs_plan", ctypes.c_int, [ctypes.POINTER(vp), i64, i64, ctypes.c_char_p]),
+    ("stencil_lcs_tile_width", ctypes.c_int, [vp]),
+    ("stencil_lcs_tile_rows", ctypes.c_int, [vp]),
+    ("stencil_lcs_run", ctypes.c_int, [vp, vp, vp, vp, vp, vp]),
+    ("stencil_lcs_destroy", ctypes.c_int, [vp]),
     ("stencil_last_error", ctypes.c_char_p, []),
     ("stencil_version", ctypes.c_char_p, []),
 ]

@@ -135,6 +135,26 @@ def test_life_plans_without_device():
     assert lib.stencil_batch_run(1, P, G, C, Tn, None) == E["TVS_E_UNSUPPORTED"]
 
 
+def test_lcs_plans_without_device():
+    lib = _lib.load()
+    p = tvs.LcsPlan(200000, 1000)
+    assert p.tile_width == 512 and p.tile_rows == 256
+    assert tvs.LcsPlan(10, 10, "w=1024").tile_width == 1024
+    assert tvs.LcsPlan(0, 0).tile_width == 512
+    assert tvs.LcsPlan(10, 10, "w=512,r=1024").tile_rows == 1024
+    assert tvs.LcsPlan(10, 10, "w=64").tile_rows == 256
+    for bad in ("w=100", "w=32", "w=8192", "k=4", "w=", "r=32", "r=2048", "w=4096,r=1024"):
+        assert code_of(lambda: tvs.LcsPlan(10, 10, bad)) == E["TVS_E_INVALID"]
+    assert code_of(lambda: tvs.LcsPlan(-1, 10)) == E["TVS_E_SHAPE"]
+    assert code_of(lambda: tvs.LcsPlan(10, 1 << 31)) == E["TVS_E_SHAPE"]
+    fake = ctypes.c_void_p(0x1000)
+    assert lib.stencil_lcs_run(p.handle if hasattr(p, "handle") else p._h, None, fake, fake,
+                               fake, None) == E["TVS_E_INVALID"]
+    assert lib.stencil_lcs_run(None, fake, fake, fake, fake, None) == E["TVS_E_INVALID"]
+    assert lib.stencil_lcs_tile_width(None) == E["TVS_E_INVALID"]
+    assert lib.stencil_lcs_destroy(None) == 0
+
+
 def test_run_argument_errors_without_device():
     lib = _lib.load()
     p = tvs.Plan((16, 16), F64, STAR, 5)
