@@ -87,6 +87,7 @@ WORKLOADS = {
     "gs2d5p": (lambda inp, n, T: inp.gs2d5p(**_kw(n, T)), "2D 5-point Gauss-Seidel FP64"),
     "gs1d3p": (lambda inp, n, T: inp.gs1d3p(**_kw(n, T)), "1D 3-point Gauss-Seidel FP64"),
     "life2d": (lambda inp, n, T: inp.life2d(**_kw(n, T)), "Game of Life B2S23, int32 cells"),
+    "gs3d7p": (lambda inp, n, T: inp.gs3d7p(**_kw(n, T)), "3D 7-point Gauss-Seidel FP64"),
     "lcs": (None, "longest common subsequence, 200000 x 200000"),
 }
 
@@ -146,7 +147,7 @@ def kernel_name(p, info, inputs) -> str:
     if info["method"] == 0:
         return "plain step"
     if p.dependence == inputs.GAUSS_SEIDEL:
-        return "gs1d sweep pipeline" if p.ndim == 1 else "gs2d wavefront"
+        return {1: "gs1d sweep pipeline", 2: "gs2d wavefront", 3: "gs3d_planes"}[p.ndim]
     if p.ndim == 1:
         return "tstp1d"
     return "tstp_reg2d" if info.get("kern", 0) == 1 else "tstp_nd"
@@ -431,12 +432,27 @@ def main():
     # dominant kernel: one band of k steps per launch (two per run, so that
     # the result lands in the caller's buffer with no copy)
     k = info["k"]
-    band_ms = time_runs(torch, lambda: plan.run(grid, p.coeffs, 2 * k), 10) / 2
-    band_updates = nu * k
+    if p.dependence == inputs.GAUSS_SEIDEL and p.ndim == 3:
+        # one launch updates one plane of every sweep in flight: the average
+        # launch of the timed solves (groups of k sweeps, planes + G (k - 1)
+        # launches each)
+        n0, n1, n2 = p.dims
+        wts, G = ((4, 2, 1), 8) if p.shape == inputs.BOX else ((1, 1, 1), 2)
+        planes = sum(w * (e - 3) for w, e in zip(wts, p.dims)) + 1
+        launches, left = 0, p.T
+        while left > 0:
+            g = min(k, left)
+            launches += planes + G * (g - 1)
+            left -= g
+        band_ms = ms / launches
+        band_updates = nu * p.T / launches
+    else:
+        band_ms = time_runs(torch, lambda: plan.run(grid, p.coeffs, 2 * k), 10) / 2
+        band_updates = nu * k
     # weighted: P products + (P-1) sums per update; Life: integer operations
     flops = band_updates * (LIFE_OPS if life else 2 * p.order - 1)
     achieved_tops = flops / (band_ms / 1e3) / 1e12
-    alg_bytes = 2 * eb * nu                          # each point read and written once per band
+    alg_bytes = 2 * eb * band_updates / k            # each point read and written once per band
     achieved_gbs = alg_bytes / (band_ms / 1e3) / 1e9
     log(f"band kernel: {band_ms:.4f} ms, {achieved_tops:.2f} TFLOP/s algorithmic, "
         f"{achieved_gbs:.0f} GB/s algorithmic")

@@ -497,10 +497,16 @@ hipError_t layout_t(const Problem& p, T* grid, void* work, hipStream_t st) {
 
 }  // namespace
 
-size_t gs_state_bytes(const Problem& p) { return p.ndim == 1 ? 256 : state_bytes(p); }
+hipError_t launch_gs3d(const Problem& p, void* work, const void* coeffs, int sweeps,
+                       hipStream_t st);
+size_t gs3d_layout_bytes(const Problem& p);
+hipError_t gs3d_layout(const Problem& p, void* grid, void* work, bool in, hipStream_t st);
+
+size_t gs_state_bytes(const Problem& p) { return p.ndim != 2 ? 256 : state_bytes(p); }
 
 size_t gs_work_bytes(const Problem& p) {
-    if (p.ndim == 1) return 256;  // status word only
+    if (p.ndim == 1) return 256;                           // status word only
+    if (p.ndim == 3) return 256 + gs3d_layout_bytes(p);  // status word, plane-major layout
     // nb bands and one slot for the bottom border row
     const size_t lay = (size_t)(bands_of(p) + 1) * (size_t)layout_width(p) * kRows * p.elem_bytes();
     return state_bytes(p) + lay;
@@ -508,18 +514,21 @@ size_t gs_work_bytes(const Problem& p) {
 
 hipError_t gs_layout_in(const Problem& p, const void* grid, void* work, hipStream_t st) {
     if (p.ndim == 1) return hipSuccess;  // the 1D kernel works on the grid itself
+    if (p.ndim == 3) return gs3d_layout(p, (void*)grid, work, true, st);
     if (p.dtype == TVS_F64) return layout_t<double, true>(p, (double*)grid, work, st);
     return layout_t<float, true>(p, (float*)grid, work, st);
 }
 
 hipError_t gs_layout_out(const Problem& p, void* grid, void* work, hipStream_t st) {
     if (p.ndim == 1) return hipSuccess;
+    if (p.ndim == 3) return gs3d_layout(p, grid, work, false, st);
     if (p.dtype == TVS_F64) return layout_t<double, false>(p, (double*)grid, work, st);
     return layout_t<float, false>(p, (float*)grid, work, st);
 }
 
 hipError_t launch_gs(const Problem& p, void* grid, const void* coeffs, int sweeps, void* work,
                      hipStream_t st) {
+    if (p.ndim == 3) return launch_gs3d(p, work, coeffs, sweeps, st);
     if (p.ndim == 1) {
         if (sweeps < 1 || sweeps > 1024 || p.dims[0] < 3) return hipErrorInvalidValue;
         const dim3 block((unsigned)(64 * ((sweeps + 63) / 64)));

@@ -90,8 +90,9 @@ std::vector<Schedule> tune_candidates(const Problem& p) {
     plain.method = TVS_METHOD_PLAIN;
     add(plain);
     if (p.dependence == TVS_GAUSS_SEIDEL) {
-        const std::initializer_list<int> ks1 = {64, 256, 1024}, ks2 = {4, 8, 16, 32, 64, 128};
-        for (int k : p.ndim == 1 ? ks1 : ks2) {
+        const std::initializer_list<int> ks1 = {64, 256, 1024}, ks2 = {4, 8, 16, 32, 64, 128},
+                                         ks3 = {16, 64, 256};
+        for (int k : p.ndim == 1 ? ks1 : p.ndim == 2 ? ks2 : ks3) {
             Schedule s = base;
             s.k = k;
             s.c = 1;

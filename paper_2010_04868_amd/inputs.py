@@ -196,12 +196,20 @@ def lcs200k(m: int = 200000, n: int = 200000) -> LcsProblem:
     return LcsProblem("lcs", m, n, 4, 9)
 
 
+def gs3d7p(n: int = 800, T: int = 200) -> Problem:
+    """3D 7-point Gauss-Seidel in place (Table 1's GS-3D size, 800^3 x 200):
+    centre 0.4, six neighbours 0.1, zero border."""
+    return Problem("gs3d7p", (n, n, n), F64, STAR, 7, GAUSS_SEIDEL, DIRICHLET,
+                   star_coeffs(3, 0.4, 0.1), T, 10, zero_border=True)
+
+
 WORKLOADS = {
     "heat1d_3p": heat1d,
     "box2d9p": box2d9p,
     "star3d7p": star3d7p,
     "gs2d5p": gs2d5p,
     "life2d": life2d,
+    "gs3d7p": gs3d7p,
 }
 
 

@@ -53,7 +53,8 @@ def code_of(fn):
     (((8, 8), F64, STAR, 5, GAUSS_SEIDEL, PERIODIC), "TVS_E_UNSUPPORTED"),
     (((8, 8), F64, STAR, 9, JACOBI, DIRICHLET), "TVS_E_UNSUPPORTED"),   # radius 2 star
     (((20,), F64, STAR, 5, JACOBI, DIRICHLET), "TVS_E_UNSUPPORTED"),    # radius 2
-    (((8, 8, 8), F64, STAR, 7, GAUSS_SEIDEL, DIRICHLET), "TVS_E_UNSUPPORTED"),
+    (((70000, 3, 3), F64, STAR, 7, GAUSS_SEIDEL, DIRICHLET), "TVS_E_UNSUPPORTED"),
+    (((8, 8, 8), F64, BOX, 27, GAUSS_SEIDEL, PERIODIC), "TVS_E_UNSUPPORTED"),
 ])
 def test_plan_validation_codes(args, err):
     assert code_of(lambda: tvs.Plan(*args)) == E[err]

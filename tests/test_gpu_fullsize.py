@@ -119,6 +119,31 @@ def test_life2d_full_size_windows():
         assert_bitwise(g, r, f"Life window at {lo}")
 
 
+def test_gs3d7p_full_size():
+    # 800^3 in place, 200 sweeps: Gauss-Seidel carries information across the
+    # whole grid in one sweep, so there is no window to cut out.  The default
+    # schedule (groups of 256 pipelined sweeps) must equal a different
+    # grouping and the composition of two shorter runs, bit for bit; the
+    # oracle checks the same kernels exactly at 120^3 x 12.
+    import torch
+
+    import paper_2010_04868_amd as tvs
+    p = inputs.gs3d7p()
+    u0 = inputs.make_grid(p)
+    got = run_gpu(p, u0)
+    g = torch.from_numpy(u0).to("cuda")
+    plan = tvs.Plan.for_problem(p, "method=tstp,k=37")
+    plan.run(g, p.coeffs, 150)
+    plan.run(g, p.coeffs, 50)
+    torch.cuda.synchronize()
+    assert_bitwise(g.cpu().numpy(), got, "GS-3D 800^3: k=37, 150 + 50 sweeps vs default")
+    del g
+    q = inputs.gs3d7p(n=120, T=12)
+    v0 = inputs.make_grid(q)
+    ref = oracle_sweep(v0, q.coeffs, q.shape, q.order, q.dependence, q.boundary, q.T)
+    assert_bitwise(run_gpu(q, v0), ref, "GS-3D 120^3 T=12")
+
+
 def test_gs2d5p_full_size_exact():
     p = inputs.gs2d5p()                  # 4096^2 in place, T = 100
     u0 = inputs.make_grid(p)

@@ -122,6 +122,28 @@ def test_gauss_seidel_1d_matches_oracle(dtype):
     assert not failures, "\n".join(failures[:20])
 
 
+@pytest.mark.parametrize("shape", [STAR, BOX])
+@pytest.mark.parametrize("dtype", [F64, F32])
+def test_gauss_seidel_3d_matches_oracle(shape, dtype):
+    # sweeps pipelined along the plane wavefront: 1, 3, 16 and the default
+    # number of sweeps per group, against one sweep per group (plain)
+    P = npoints(3, shape)
+    coeffs = _coeffs(P, seed=70 + shape)
+    failures = []
+    for dims in [(3, 3, 3), (5, 6, 7), (17, 19, 23), (34, 20, 41), (20, 33, 9), (9, 4, 70)]:
+        u0 = np.random.default_rng(sum(dims)).random(dims).astype(np_dtype(dtype))
+        for T in (1, 2, 5, 9):
+            ref = oracle_sweep(u0, coeffs, shape, P, GAUSS_SEIDEL, DIRICHLET, T)
+            for tuning in ("method=plain", "method=tstp,k=1", "method=tstp,k=3",
+                           "method=tstp,k=16", None):
+                got = gpu_sweep(u0, coeffs, shape, P, GAUSS_SEIDEL, DIRICHLET, T, tuning)
+                try:
+                    assert_bitwise(got, ref, f"GS-3D dims={dims} T={T} tuning={tuning}")
+                except AssertionError as e:
+                    failures.append(str(e))
+    assert not failures, "\n".join(failures[:20])
+
+
 def test_zero_steps_is_noop():
     u0 = np.random.default_rng(0).random((40, 50))
     got = gpu_sweep(u0, [1.0 / 9] * 9, BOX, 9, JACOBI, DIRICHLET, 0)
