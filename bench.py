@@ -88,6 +88,7 @@ WORKLOADS = {
     "gs1d3p": (lambda inp, n, T: inp.gs1d3p(**_kw(n, T)), "1D 3-point Gauss-Seidel FP64"),
     "life2d": (lambda inp, n, T: inp.life2d(**_kw(n, T)), "Game of Life B2S23, int32 cells"),
     "gs3d7p": (lambda inp, n, T: inp.gs3d7p(**_kw(n, T)), "3D 7-point Gauss-Seidel FP64"),
+    "star1d5p": (lambda inp, n, T: inp.star1d5p(**_kw(n, T)), "1D 5-point (radius 2) Jacobi FP64"),
     "lcs": (None, "longest common subsequence, 200000 x 200000"),
 }
 
@@ -149,7 +150,7 @@ def kernel_name(p, info, inputs) -> str:
     if p.dependence == inputs.GAUSS_SEIDEL:
         return {1: "gs1d sweep pipeline", 2: "gs2d wavefront", 3: "gs3d_planes"}[p.ndim]
     if p.ndim == 1:
-        return "tstp1d"
+        return "tstp1d_r" if info.get("radius", 1) > 1 else "tstp1d"
     return "tstp_reg2d" if info.get("kern", 0) == 1 else "tstp_nd"
 
 

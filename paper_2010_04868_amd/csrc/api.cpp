@@ -67,6 +67,9 @@ int ensure_scratch(tvs_plan* p) {
     return TVS_OK;
 }
 
+hipError_t launch_tstp1d_radius(const Problem& p, const BandGeom& g, const void* in, void* out,
+                                const void* coeffs, hipStream_t st);
+
 // Enqueue T Jacobi steps: bands of sched.k levels (plain: single steps),
 // ping-ponging between the caller's grid and the plan's second buffer.
 int enqueue_jacobi(tvs_plan* p, void* grid, const CoeffBuf& cb, int64_t T, hipStream_t st) {
@@ -101,7 +104,10 @@ int enqueue_jacobi(tvs_plan* p, void* grid, const CoeffBuf& cb, int64_t T, hipSt
                 done += kb;
                 continue;
             }
-            TVS_HIP_TRY(launch_tstp_band(pr, g, buf[cur], buf[1 - cur], cb.bytes, st));
+            if (pr.radius > 1)
+                TVS_HIP_TRY(launch_tstp1d_radius(pr, g, buf[cur], buf[1 - cur], cb.bytes, st));
+            else
+                TVS_HIP_TRY(launch_tstp_band(pr, g, buf[cur], buf[1 - cur], cb.bytes, st));
             cur ^= 1;
             done += kb;
         }

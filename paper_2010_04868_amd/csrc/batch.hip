@@ -616,6 +616,8 @@ extern "C" int stencil_batch_run(int n, tvs_plan* const* plans, void* const* gri
     for (int i = 0; i < n; ++i) {
         if (plans[i] && plans[i]->prob.rule == TVS_RULE_LIFE)
             return set_error(TVS_E_UNSUPPORTED, "Game of Life plans do not run in batches");
+        if (plans[i] && plans[i]->prob.radius > 1)
+            return set_error(TVS_E_UNSUPPORTED, "plans of radius > 1 do not run in batches");
         if (!plans[i] || !grids[i] || !coeffs[i]) return set_error(TVS_E_INVALID, "NULL member");
         if (T[i] < 0) return set_error(TVS_E_INVALID, "T < 0");
     }

@@ -208,8 +208,12 @@ hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t st)
     return hipGetLastError();
 }
 
+hipError_t launch_plain_radius(const Problem& p, const void* in, void* out, const void* coeffs,
+                               hipStream_t st);
+
 hipError_t launch_plain_step(const Problem& p, const void* in, void* out, const void* coeffs,
                              hipStream_t st) {
+    if (p.radius > 1) return launch_plain_radius(p, in, out, coeffs, st);
     if (p.rule == TVS_RULE_LIFE) {
         const int n0 = (int)p.dims[0], n1 = (int)p.dims[1];
         constexpr int ry = 8;

@@ -15,6 +15,9 @@ namespace tvs {
 
 static thread_local std::string g_last_error;
 
+bool radius_supported(int ndim, int shape, int r);
+size_t tstp1d_radius_lds_bytes(const Problem& p, int k, int Lv);
+
 int set_error(int code, const std::string& msg) {
     g_last_error = msg;
     return code;
@@ -65,7 +68,14 @@ int validate(Problem* pr, int ndim, const int64_t* dims, int dtype, int shape, i
         if (total > ((int64_t)1 << 40) / dims[a]) return set_error(TVS_E_SHAPE, "size overflow");
         total *= dims[a];
     }
-    if (r != 1) return set_error(TVS_E_UNSUPPORTED, "only radius 1 stencils are implemented");
+    if (r != 1 && dependence == TVS_GAUSS_SEIDEL)
+        return set_error(TVS_E_UNSUPPORTED, "Gauss-Seidel is implemented for radius 1");
+    if (r != 1 && !radius_supported(ndim, shape, r))
+        return set_error(TVS_E_UNSUPPORTED, "radius " + std::to_string(r) + " " +
+                                                (shape == TVS_BOX ? "box" : "star") + " in " +
+                                                std::to_string(ndim) +
+                                                "D: radius 2 and 3 stars, the 1D radius 3 and the "
+                                                "2D radius 2 box (at most 27 weights) are implemented");
     if (dependence == TVS_GAUSS_SEIDEL && boundary == TVS_PERIODIC)
         return set_error(TVS_E_UNSUPPORTED, "Gauss-Seidel with a periodic boundary");
     if (dependence == TVS_GAUSS_SEIDEL && ndim == 3 && dims[0] - 2 > 65535)
@@ -211,6 +221,19 @@ Schedule default_schedule(const Problem& p) {
         return s;
     }
     const bool f64 = p.dtype == TVS_F64;
+    if (p.radius > 1) {
+        // radius > 1: the 1D pipeline (skew r + 1); 2D and 3D run plain steps
+        if (p.ndim != 1) {
+            Schedule plain;
+            plain.method = TVS_METHOD_PLAIN;
+            return plain;
+        }
+        s.s = p.radius + 1;
+        s.pl = 64;
+        s.k = 64;
+        s.l = 128;  // measured best on 1e5 points, radius 2 (64..512 tried)
+        return s;
+    }
     if (p.ndim == 1) {
         s.pl = 64;
         s.k = 64;
@@ -273,9 +296,21 @@ int check_schedule(const Problem& p, const Schedule& s) {
             return set_error(TVS_E_INVALID, "c (rows per lane) must be 1 for Gauss-Seidel");
         return TVS_OK;
     }
-    if (s.s != 2)
+    if (p.radius > 1) {
+        if (p.ndim != 1)
+            return set_error(TVS_E_INVALID, "the time-skewed pipeline for radius > 1 is 1D only; "
+                                            "use method=plain");
+        if (s.s != p.radius + 1)
+            return set_error(TVS_E_INVALID, "skew s = r + 1 is the legal choice for radius r "
+                                            "(s > max dx/dt)");
+        if (s.pl != 64 || s.k > 64)
+            return set_error(TVS_E_INVALID, "radius > 1: 64-lane pipelines (pl=64), k <= 64");
+        if (tstp1d_radius_lds_bytes(p, s.k, s.l > 0 ? s.l : 256) > 160 * 1024)
+            return set_error(TVS_E_INVALID, "segment too long for LDS: " + format_tuning(p, s));
+    } else if (s.s != 2) {
         return set_error(TVS_E_INVALID, "skew s = 2 is the only legal choice for radius 1 "
                                         "(s > max dx/dt) with one barrier per step");
+    }
     // the full band must fit; shallower remainder bands that do not fit the
     // tile shape run as plain steps
     BandGeom g;

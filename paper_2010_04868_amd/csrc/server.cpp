@@ -401,6 +401,8 @@ int stencil_server_submit(tvs_server* s, const tvs_request* rq, uint64_t* id) {
     auto* r = new Req();
     int rc = validate(&r->prob, rq->ndim, rq->dims, rq->dtype, rq->shape, rq->order,
                       rq->dependence, rq->boundary);
+    if (rc == TVS_OK && r->prob.radius > 1)
+        rc = set_error(TVS_E_UNSUPPORTED, "the server takes radius-1 stencils");
     if (rc == TVS_OK) rc = size_request(r);
     if (rc) {
         if (r->plan) stencil_plan_destroy(r->plan);

@@ -138,6 +138,12 @@ def heat1d(periodic: bool = False, n: int = 100000, T: int = 1000) -> Problem:
                    JACOBI, PERIODIC if periodic else DIRICHLET, (0.25, 0.5, 0.25), T, 1)
 
 
+def star1d5p(n: int = 100000, T: int = 1000) -> Problem:
+    """1D 5-point (radius 2) Jacobi, weights (0.05, 0.2, 0.5, 0.2, 0.05), fixed ends."""
+    return Problem("star1d5p", (n,), F64, STAR, 5, JACOBI, DIRICHLET,
+                   (0.05, 0.2, 0.5, 0.2, 0.05), T, 11)
+
+
 def gs1d3p(n: int = 100000, T: int = 1000) -> Problem:
     """1D 3-point Gauss-Seidel in place, coefficients (1/4, 1/2, 1/4), fixed ends."""
     return Problem("gs1d3p", (n,), F64, STAR, 3, GAUSS_SEIDEL, DIRICHLET, (0.25, 0.5, 0.25), T, 6)
@@ -210,6 +216,7 @@ WORKLOADS = {
     "gs2d5p": gs2d5p,
     "life2d": life2d,
     "gs3d7p": gs3d7p,
+    "star1d5p": star1d5p,
 }
 
 

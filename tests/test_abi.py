@@ -51,8 +51,10 @@ def code_of(fn):
     (((8, 8), F64, STAR, 5, 4, DIRICHLET), "TVS_E_INVALID"),
     (((8, 8), F64, STAR, 5, JACOBI, 5), "TVS_E_INVALID"),
     (((8, 8), F64, STAR, 5, GAUSS_SEIDEL, PERIODIC), "TVS_E_UNSUPPORTED"),
-    (((8, 8), F64, STAR, 9, JACOBI, DIRICHLET), "TVS_E_UNSUPPORTED"),   # radius 2 star
-    (((20,), F64, STAR, 5, JACOBI, DIRICHLET), "TVS_E_UNSUPPORTED"),    # radius 2
+    (((9, 9, 9), F64, BOX, 125, JACOBI, DIRICHLET), "TVS_E_UNSUPPORTED"),  # 125 weights
+    (((9, 9), F64, BOX, 49, JACOBI, DIRICHLET), "TVS_E_UNSUPPORTED"),      # radius 3 box
+    (((20,), F64, STAR, 9, JACOBI, DIRICHLET), "TVS_E_UNSUPPORTED"),       # radius 4
+    (((20,), F64, STAR, 5, GAUSS_SEIDEL, DIRICHLET), "TVS_E_UNSUPPORTED"),  # radius 2 GS
     (((70000, 3, 3), F64, STAR, 7, GAUSS_SEIDEL, DIRICHLET), "TVS_E_UNSUPPORTED"),
     (((8, 8, 8), F64, BOX, 27, GAUSS_SEIDEL, PERIODIC), "TVS_E_UNSUPPORTED"),
 ])
@@ -103,6 +105,27 @@ def test_huge_plane_runs_plain():
     assert p.info()["method"] == 0
     assert code_of(lambda: tvs.Plan((3, 16384, 16384), F64, STAR, 7,
                                     tuning="method=tstp,k=2,w=64,h=32,c=8")) == E["TVS_E_INVALID"]
+
+
+def test_radius_plans_without_device():
+    p = tvs.Plan((1000,), F64, STAR, 5)              # radius 2: the 1D pipeline, skew 3
+    inf = p.info()
+    assert inf["radius"] == 2 and inf["method"] == 1 and inf["s"] == 3 and inf["pl"] == 64
+    assert tvs.Plan((50, 60), F64, BOX, 25).info()["method"] == 0      # 2D radius 2: plain
+    assert tvs.Plan((9, 9, 9), F32, STAR, 19).info()["radius"] == 3     # 3D radius 3 star
+    q = tvs.Plan((1000,), F64, STAR, 7, tuning="method=tstp,k=16,l=100")
+    assert q.info()["k"] == 16 and q.info()["s"] == 4
+    for bad in ("method=tstp,k=8,l=64,pl=16", "method=tstp,k=8,s=2", "method=tstp,k=8,l=4000"):
+        assert code_of(lambda: tvs.Plan((1000,), F64, STAR, 5, tuning=bad)) == E["TVS_E_INVALID"]
+    assert code_of(lambda: tvs.Plan((50, 60), F64, STAR, 9, tuning="method=tstp,k=4")) \
+        == E["TVS_E_INVALID"]
+    lib = _lib.load()
+    P = (ctypes.c_void_p * 1)(p.handle.value)
+    G = (ctypes.c_void_p * 1)(0x1000)
+    c = (ctypes.c_double * 5)(*([0.2] * 5))
+    C = (ctypes.POINTER(ctypes.c_double) * 1)(ctypes.cast(c, ctypes.POINTER(ctypes.c_double)))
+    Tn = (ctypes.c_int64 * 1)(3)
+    assert lib.stencil_batch_run(1, P, G, C, Tn, None) == E["TVS_E_UNSUPPORTED"]
 
 
 def test_life_plans_without_device():

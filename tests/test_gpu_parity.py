@@ -144,6 +144,41 @@ def test_gauss_seidel_3d_matches_oracle(shape, dtype):
     assert not failures, "\n".join(failures[:20])
 
 
+RADIUS_SIZES = {1: [(5,), (7,), (97,), (1000,), (4099,)],
+                2: [(5, 5), (7, 9), (37, 53), (70, 130)],
+                3: [(5, 5, 5), (7, 8, 9), (17, 19, 23)]}
+RADIUS_TUNINGS = {1: [None, "method=plain", "method=tstp,k=1,l=16", "method=tstp,k=7,l=20",
+                      "method=tstp,k=64,l=100", "method=tstp,k=20,l=37"],
+                  2: [None, "method=plain"], 3: [None, "method=plain"]}
+
+
+@pytest.mark.parametrize("ndim,shape,order", [(1, STAR, 5), (1, STAR, 7), (1, BOX, 5),
+                                              (2, STAR, 9), (2, BOX, 25), (2, STAR, 13),
+                                              (3, STAR, 13), (3, STAR, 19)])
+@pytest.mark.parametrize("boundary", [DIRICHLET, PERIODIC])
+@pytest.mark.parametrize("dtype", [F64, F32])
+def test_radius_matches_oracle(ndim, shape, order, boundary, dtype):
+    # radius 2 and 3: the 1D pipeline with skew r + 1 (every depth, ragged
+    # segments, remainder bands) and the plain step in 1D, 2D and 3D
+    r = {(1, 5): 2, (1, 7): 3, (2, 9): 2, (2, 25): 2, (2, 13): 3, (3, 13): 2, (3, 19): 3}[
+        (ndim, order)]
+    coeffs = _coeffs(order, seed=80 + order)
+    failures = []
+    for dims in RADIUS_SIZES[ndim]:
+        if min(dims) < 2 * r + 1:
+            continue
+        u0 = np.random.default_rng(sum(dims) + r).random(dims).astype(np_dtype(dtype))
+        for T in STEPS + ([70] if ndim == 1 else []):
+            ref = oracle_sweep(u0, coeffs, shape, order, JACOBI, boundary, T)
+            for tuning in RADIUS_TUNINGS[ndim]:
+                got = gpu_sweep(u0, coeffs, shape, order, JACOBI, boundary, T, tuning)
+                try:
+                    assert_bitwise(got, ref, f"r={r} dims={dims} T={T} tuning={tuning}")
+                except AssertionError as e:
+                    failures.append(str(e))
+    assert not failures, "\n".join(failures[:20])
+
+
 def test_zero_steps_is_noop():
     u0 = np.random.default_rng(0).random((40, 50))
     got = gpu_sweep(u0, [1.0 / 9] * 9, BOX, 9, JACOBI, DIRICHLET, 0)

@@ -158,6 +158,9 @@ BRUTE_CASES = [
     ((7, 6), STAR, 2, 3),
     ((4, 4, 5), STAR, 1, 3),
     ((4, 4, 5), BOX, 1, 2),
+    ((6, 7), BOX, 2, 2),
+    ((5, 5, 6), STAR, 2, 2),
+    ((17,), STAR, 3, 3),
 ]
 
 
