@@ -39,6 +39,12 @@ def _load():
         fn.argtypes = [ctypes.c_int, i64p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                        ctypes.POINTER(real), ctypes.c_int64, ctypes.POINTER(real)]
         fn.restype = ctypes.c_int
+    for name, real in (("oracle_sweep_f64_varcoef", ctypes.c_double),
+                       ("oracle_sweep_f32_varcoef", ctypes.c_float)):
+        fn = getattr(lib, name)
+        fn.argtypes = [ctypes.c_int, i64p, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                       ctypes.POINTER(real), ctypes.c_int64, ctypes.POINTER(real)]
+        fn.restype = ctypes.c_int
     lib.oracle_offsets.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                    ctypes.POINTER(ctypes.c_int)]
     lib.oracle_offsets.restype = ctypes.c_int
@@ -137,3 +143,25 @@ def lcs(a, b, row=None, col=None):
     if rc != 0:
         raise OracleError(f"oracle lcs failed ({rc})")
     return r, c
+
+
+def sweep_varcoef(u: np.ndarray, weights: np.ndarray, shape: int, boundary: int, T: int,
+                  npoints: int, precision: str = "f64") -> np.ndarray:
+    """Jacobi sweep with a weight per offset per point (variable coefficients,
+    fixed over time): ``weights`` has shape (npoints,) + u.shape, offsets in
+    canonical order.  Same operation order as ``sweep``; the input is not
+    modified."""
+    lib = _load()
+    real = np.float64 if precision == "f64" else np.float32
+    ct = ctypes.c_double if precision == "f64" else ctypes.c_float
+    g = np.ascontiguousarray(u, dtype=real).copy()
+    w = np.ascontiguousarray(weights, dtype=real)
+    if w.shape != (npoints,) + g.shape:
+        raise OracleError("weights must have shape (npoints,) + grid shape")
+    dims = (ctypes.c_int64 * g.ndim)(*g.shape)
+    fn = lib.oracle_sweep_f64_varcoef if precision == "f64" else lib.oracle_sweep_f32_varcoef
+    rc = fn(g.ndim, dims, shape, npoints, boundary, w.ctypes.data_as(ctypes.POINTER(ct)), int(T),
+            g.ctypes.data_as(ctypes.POINTER(ct)))
+    if rc != 0:
+        raise OracleError(f"oracle varcoef sweep failed ({rc})")
+    return g

@@ -137,14 +137,18 @@ static int prepare(int ndim, const int64_t *dims, int shape, int npts, int depen
  * leading unit axes for ndim < 3; a unit axis has a single index and a zero
  * offset component, which leaves the lexicographic order unchanged.
  */
+/* wts == NULL: the weights are coeffs[q] at every point; otherwise the weight
+ * of offset q at the point with C-order index i is wts[q * N + i] (N grid
+ * points), fixed over time -- a variable-coefficient stencil. */
 #define DEFINE_SWEEP(NAME, REAL)                                                          \
-int NAME(int ndim, const int64_t *dims, int shape, int npoints, int dependence,           \
-         int boundary, const REAL *coeffs, int64_t T, REAL *grid)                         \
+static int NAME##_impl(int ndim, const int64_t *dims, int shape, int npoints,            \
+                       int dependence, int boundary, const REAL *coeffs, const REAL *wts, \
+                       int64_t T, REAL *grid)                                             \
 {                                                                                         \
     int r = 0;                                                                            \
     int offs[MAXP][MAXD];                                                                 \
     int64_t n[MAXD];                                                                      \
-    if (!coeffs || !grid) return -1;                                                      \
+    if ((!coeffs && !wts) || !grid) return -1;                                            \
     int P = prepare(ndim, dims, shape, npoints, dependence, boundary, T, &r, offs, n);   \
     if (P < 0) return P;                                                                  \
     if (dependence == ORACLE_GAUSS_SEIDEL && boundary == ORACLE_PERIODIC) return -4;      \
@@ -191,7 +195,8 @@ int NAME(int ndim, const int64_t *dims, int shape, int npoints, int dependence, 
                             int64_t kk = wrap(k + o[q][2], ext[2]);                       \
                             v = src[(ii * ext[1] + jj) * ext[2] + kk];                    \
                         }                                                                 \
-                        REAL term = coeffs[q] * v;                                        \
+                        REAL wq = wts ? wts[(int64_t)q * total + at] : coeffs[q];         \
+                        REAL term = wq * v;                                               \
                         acc = (q == 0) ? term : acc + term;                               \
                     }                                                                     \
                     dst[at] = acc;                                                        \
@@ -203,6 +208,20 @@ int NAME(int ndim, const int64_t *dims, int shape, int npoints, int dependence, 
         free(spare);                                                                      \
     }                                                                                     \
     return 0;                                                                             \
+}                                                                                         \
+int NAME(int ndim, const int64_t *dims, int shape, int npoints, int dependence,           \
+         int boundary, const REAL *coeffs, int64_t T, REAL *grid)                         \
+{                                                                                         \
+    if (!coeffs) return -1;                                                               \
+    return NAME##_impl(ndim, dims, shape, npoints, dependence, boundary, coeffs, NULL, T, \
+                       grid);                                                             \
+}                                                                                         \
+int NAME##_varcoef(int ndim, const int64_t *dims, int shape, int npoints, int boundary,  \
+                   const REAL *weights, int64_t T, REAL *grid)                            \
+{                                                                                         \
+    if (!weights) return -1;                                                              \
+    return NAME##_impl(ndim, dims, shape, npoints, ORACLE_JACOBI, boundary, NULL,        \
+                       weights, T, grid);                                                 \
 }
 
 DEFINE_SWEEP(oracle_sweep_f64, double)

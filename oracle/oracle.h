@@ -28,4 +28,12 @@ int oracle_sweep_f64(int ndim, const int64_t *dims, int shape, int npoints, int 
                      int boundary, const double *coeffs, int64_t T, double *grid);
 int oracle_sweep_f32(int ndim, const int64_t *dims, int shape, int npoints, int dependence,
                      int boundary, const float *coeffs, int64_t T, float *grid);
+/* Variable-coefficient Jacobi sweep (Section 3.4: LCS treats one sequence as
+ * a coefficient that varies along the space axis): the weight of offset q at
+ * the point with C-order index i is weights[q * N + i], N = prod(dims), the
+ * same at every step.  Otherwise as oracle_sweep_*. */
+int oracle_sweep_f64_varcoef(int ndim, const int64_t *dims, int shape, int npoints, int boundary,
+                             const double *weights, int64_t T, double *grid);
+int oracle_sweep_f32_varcoef(int ndim, const int64_t *dims, int shape, int npoints, int boundary,
+                             const float *weights, int64_t T, float *grid);
 #endif

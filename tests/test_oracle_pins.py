@@ -599,3 +599,54 @@ def test_lcs_rectangles_chain_through_wavefront_arrays():
     assert np.array_equal(np.concatenate([rows[0]] + [rows[j][1:] for j in range(1, 4)]), row)
     assert np.array_equal(np.concatenate([cols[0]] + [cols[i][1:] for i in range(1, 3)])[1:],
                           col[1:])
+
+
+# Variable coefficients (a weight per offset per point, fixed over time; the
+# paper's LCS treats one sequence as such a coefficient, Section 3.4): exact
+# integer brute force through the dense iteration matrix, and the reduction
+# to the constant-coefficient sweep when every point carries the same weights.
+def varcoef_bruteforce(u0, shape, r, W, boundary, T):
+    dims = u0.shape
+    n = int(np.prod(dims))
+    offs = offset_list(len(dims), shape, r)
+    A = np.zeros((n, n), dtype=object)
+    A[:] = 0
+    for idx in itertools.product(*[range(k) for k in dims]):
+        i = int(np.ravel_multi_index(idx, dims))
+        if not is_updated(idx, dims, r, boundary):
+            A[i, i] = 1
+            continue
+        for q, d in enumerate(offs):
+            j = int(np.ravel_multi_index(neighbour(idx, d, dims), dims))
+            A[i, j] += int(W[q][idx])
+    v = np.array([int(x) for x in u0.ravel()], dtype=object)
+    for _ in range(T):
+        v = A.dot(v)
+    return v.reshape(dims)
+
+
+@pytest.mark.parametrize("dims,shape,r,T", [((12,), STAR, 1, 4), ((13,), STAR, 2, 3),
+                                            ((5, 6), STAR, 1, 3), ((5, 6), BOX, 1, 2),
+                                            ((4, 4, 5), STAR, 1, 2)])
+@pytest.mark.parametrize("boundary", [DIRICHLET, PERIODIC])
+def test_varcoef_exact_bruteforce(dims, shape, r, T, boundary):
+    P = len(offset_list(len(dims), shape, r))
+    W = np.random.default_rng(P + T).integers(-2, 3, size=(P,) + dims).astype(np.float64)
+    u0 = int_inputs(dims, seed=sum(dims) + 1)
+    exact = varcoef_bruteforce(u0, shape, r, W, boundary, T)
+    assert max(abs(int(x)) for x in exact.ravel()) < 2 ** 53
+    got = oracle.sweep_varcoef(u0, W, shape, boundary, T, P)
+    assert np.array_equal(got, exact.astype(np.float64))
+
+
+@pytest.mark.parametrize("dims,shape,P", [((40,), STAR, 5), ((9, 11), BOX, 9), ((6, 7, 8), STAR, 7)])
+@pytest.mark.parametrize("boundary", [DIRICHLET, PERIODIC])
+def test_varcoef_constant_weights_reduce_to_sweep(dims, shape, P, boundary):
+    rng = np.random.default_rng(P)
+    c = rng.uniform(0.02, 0.2, P)
+    u0 = rng.random(dims)
+    W = np.broadcast_to(c.reshape((P,) + (1,) * len(dims)), (P,) + dims)
+    for prec in ("f64", "f32"):
+        a = oracle.sweep_varcoef(u0, W, shape, boundary, 7, P, precision=prec)
+        b = oracle.sweep(u0, list(c), shape, JACOBI, boundary, 7, npoints=P, precision=prec)
+        assert np.array_equal(a, b)
