@@ -90,6 +90,7 @@ WORKLOADS = {
     "gs3d7p": (lambda inp, n, T: inp.gs3d7p(**_kw(n, T)), "3D 7-point Gauss-Seidel FP64"),
     "star1d5p": (lambda inp, n, T: inp.star1d5p(**_kw(n, T)), "1D 5-point (radius 2) Jacobi FP64"),
     "lcs": (None, "longest common subsequence, 200000 x 200000"),
+    "vc1d3p": (None, "1D 3-point Jacobi with variable coefficients FP64"),
 }
 
 # Integer operations of one LCS cell in the branch-free form of the
@@ -364,6 +365,67 @@ def lcs_bench(torch, tvs, inputs, args, copy_gbs):
     return out
 
 
+def varcoef_bench(torch, tvs, inputs, args, copy_gbs):
+    """1D variable-coefficient Jacobi (a weight per point and offset), 1e5
+    points x 1000 steps: the time-skewed pipeline with the weights staged in
+    LDS against plain steps reading them from memory."""
+    import oracle
+    p = inputs.vc1d3p(**_kw(args.n, args.T))
+    u0 = inputs.make_grid(p)
+    W = inputs.varcoef_weights(p)
+    grid = torch.from_numpy(u0).to("cuda")
+    w = torch.from_numpy(W).to("cuda")
+    plan = tvs.Plan.for_problem(p, args.tuning)
+    info = plan.info()
+    for _ in range(1 + args.warmup):
+        plan.run_varcoef(grid, w, p.T)
+    torch.cuda.synchronize()
+    ms = time_runs(torch, lambda: plan.run_varcoef(grid, w, p.T), args.steps)
+    nu = p.updated_points()
+    value = nu * p.T / (ms / 1e3) / 1e9
+    k = info["k"]
+    band_ms = time_runs(torch, lambda: plan.run_varcoef(grid, w, 2 * k), 10) / 2
+    ops = nu * k * (2 * p.order - 1)
+    achieved = ops / (band_ms / 1e3) / 1e12
+    plain = tvs.Plan.for_problem(p, "method=plain")
+    plain.run_varcoef(grid, w, p.T)
+    plain_ms = time_runs(torch, lambda: plain.run_varcoef(grid, w, p.T), args.plain_steps)
+    plain_value = nu * p.T / (plain_ms / 1e3) / 1e9
+    log(f"varcoef: {plan.tuning()} {ms:.3f} ms/solve, {value:.1f} GStencil/s; band {band_ms:.4f} ms; "
+        f"plain {plain_value:.1f} GStencil/s")
+    out = {
+        "metric": METRIC, "value": round(value, 2), "unit": "GStencil/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": f"synthetic: uniform[0,1) grid, diffusivity uniform[0.1,0.4], PCG64(seed {p.seed})",
+        "config": {"workload": f"1D 3-point Jacobi with variable coefficients {p.dims[0]} FP64, "
+                               f"T={p.T}, fixed ends, weights (a, 1-2a, a) per point",
+                   "schedule": plan.tuning(), "updated_points": nu},
+        "copy_GBs": round(copy_gbs, 1),
+        "plain_sweep": {"value": round(plain_value, 2), "unit": "GStencil/s",
+                        "speedup": round(value / plain_value, 3)},
+        "roofline": {"bound": "alu", "achieved": round(achieved, 3),
+                     "peak": round(ALU_PEAK_TOPS, 2), "unit": "TFLOP/s",
+                     "frac": round(achieved / ALU_PEAK_TOPS, 4), "traffic": None,
+                     "kernel": "tstp1d_r with LDS-staged weights (one launch of k steps)",
+                     "kernel_ms": round(band_ms, 4),
+                     "algorithmic_bytes": (2 + p.order) * 8 * nu},
+    }
+    if not args.no_cpu:
+        t0 = time.perf_counter()
+        oracle.sweep_varcoef(u0, W, p.shape, p.boundary, 50, p.order)
+        one = (time.perf_counter() - t0) / 50
+        steps = max(1, min(p.T, int(15.0 / max(one, 1e-9))))
+        t0 = time.perf_counter()
+        oracle.sweep_varcoef(u0, W, p.shape, p.boundary, steps, p.order)
+        dt = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": round(nu * steps / dt / 1e9, 4), "unit": "GStencil/s",
+                               "cores": 1, "kind": "oracle",
+                               "sample": f"{steps} of {p.T} steps of the same grid, single thread, "
+                                         f"{dt:.1f} s"}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -404,6 +466,9 @@ def main():
 
     if args.workload == "lcs":
         print(json.dumps(lcs_bench(torch, tvs, inputs, args, copy_gbs)), flush=True)
+        return
+    if args.workload == "vc1d3p":
+        print(json.dumps(varcoef_bench(torch, tvs, inputs, args, copy_gbs)), flush=True)
         return
     p = WORKLOADS[args.workload][0](inputs, args.n, args.T)
     u0 = inputs.make_grid(p)

@@ -172,6 +172,21 @@ int stencil_plan_destroy(tvs_plan *plan);
  */
 int stencil_run(tvs_plan *plan, void *grid, const double *coeffs, int64_t T, void *stream);
 
+/*
+ * Advance grid by T Jacobi steps of a variable-coefficient stencil: the
+ * weight of offset q at the point with C-order index i is weights[q * N + i]
+ * (N = prod(dims), offsets in canonical order), the same at every step
+ * (Section 3.4 treats LCS's sequence B as such a coefficient, one that varies
+ * along the space axis).  Each update is w_0(i)*v_0 + w_1(i)*v_1 + ... in
+ * the order and rounding stated above.
+ *   weights  device, P * N elements of the plan's dtype (F32 or F64); read
+ *            only, not retained
+ * Jacobi plans only (Gauss-Seidel: TVS_E_UNSUPPORTED; Life: TVS_E_INVALID).
+ * 1D plans with a time-skewed schedule run bands of up to 64 levels with the
+ * weights staged in LDS; 2D and 3D plans run one step per launch.
+ */
+int stencil_run_varcoef(tvs_plan *plan, void *grid, const void *weights, int64_t T, void *stream);
+
 /* One-call form: plans (through an internal cache keyed by the problem) and runs. */
 int stencil_run_simple(void *grid, int ndim, const int64_t *dims, int dtype, const double *coeffs,
                        int shape, int order, int dependence, int boundary, int64_t T,

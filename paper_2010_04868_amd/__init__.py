@@ -106,6 +106,19 @@ class Plan:
         check(load().stencil_run(self._h, ctypes.c_void_p(grid.data_ptr()), c, int(T),
                                  ctypes.c_void_p(_stream_handle(stream))))
 
+    def run_varcoef(self, grid, weights, T: int, stream=None) -> None:
+        """T Jacobi steps with a weight per offset per point: ``weights`` is a
+        device tensor of shape (order,) + dims in the grid's dtype."""
+        if tuple(grid.shape) != self.dims or _dtype_of(grid) != self.dtype:
+            raise ValueError("grid shape/dtype does not match the plan")
+        if (tuple(weights.shape) != (self.order,) + self.dims or weights.dtype != grid.dtype
+                or not weights.is_contiguous() or not weights.is_cuda):
+            raise ValueError("weights must be a contiguous device tensor of shape "
+                             "(order,) + dims in the grid's dtype")
+        check(load().stencil_run_varcoef(self._h, ctypes.c_void_p(grid.data_ptr()),
+                                         ctypes.c_void_p(weights.data_ptr()), int(T),
+                                         ctypes.c_void_p(_stream_handle(stream))))
+
     def tune(self, grid, coeffs: Optional[Sequence[float]], T_probe: int, stream=None) -> str:
         buf = ctypes.create_string_buffer(256)
         c = None if coeffs is None else _coeff_array(coeffs)

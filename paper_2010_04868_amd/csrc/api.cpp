@@ -69,6 +69,11 @@ int ensure_scratch(tvs_plan* p) {
 
 hipError_t launch_tstp1d_radius(const Problem& p, const BandGeom& g, const void* in, void* out,
                                 const void* coeffs, hipStream_t st);
+size_t tstp1d_vc_lds_bytes(const Problem& p, int k, int Lv);
+hipError_t launch_plain_varcoef(const Problem& p, const void* in, void* out, const void* wts,
+                                hipStream_t st);
+hipError_t launch_tstp1d_varcoef(const Problem& p, int k, int Lv, const void* in, void* out,
+                                 const void* wts, hipStream_t st);
 
 // Enqueue T Jacobi steps: bands of sched.k levels (plain: single steps),
 // ping-ponging between the caller's grid and the plan's second buffer.
@@ -378,6 +383,45 @@ int stencil_run_simple(void* grid, int ndim, const int64_t* dims, int dtype, con
         }
     }
     return stencil_run(p, grid, coeffs, T, stream);
+}
+
+int stencil_run_varcoef(tvs_plan* p, void* grid, const void* weights, int64_t T, void* stream) {
+    clear_error();
+    if (!p || !grid || !weights) return set_error(TVS_E_INVALID, "NULL argument");
+    if (T < 0) return set_error(TVS_E_INVALID, "T < 0");
+    if (p->prob.rule == TVS_RULE_LIFE)
+        return set_error(TVS_E_INVALID, "Game of Life plans have no weights");
+    if (p->prob.dependence != TVS_JACOBI)
+        return set_error(TVS_E_UNSUPPORTED, "variable coefficients: Jacobi plans only");
+    if (T == 0) return TVS_OK;
+    int rc = ensure_scratch(p);
+    if (rc) return rc;
+    const Problem& pr = p->prob;
+    hipStream_t st = (hipStream_t)stream;
+    void* buf[2] = {grid, p->scratch};
+    int cur = 0;
+    // 1D time-skewed schedules run bands of up to k levels (64-lane
+    // pipelines); everything else, and a band whose weights do not fit LDS,
+    // runs plain steps
+    const bool band = pr.ndim == 1 && p->sched.method == TVS_METHOD_TSTP;
+    const int k = std::max(1, std::min(64, p->sched.k));
+    const int Lv = p->sched.l > 0 ? p->sched.l : 256;
+    int64_t done = 0;
+    while (done < T) {
+        const int kb = (int)std::min<int64_t>(band ? k : 1, T - done);
+        if (band && tstp1d_vc_lds_bytes(pr, kb, Lv) <= 160 * 1024) {
+            TVS_HIP_TRY(launch_tstp1d_varcoef(pr, kb, Lv, buf[cur], buf[1 - cur], weights, st));
+            cur ^= 1;
+        } else {
+            for (int t = 0; t < kb; ++t) {
+                TVS_HIP_TRY(launch_plain_varcoef(pr, buf[cur], buf[1 - cur], weights, st));
+                cur ^= 1;
+            }
+        }
+        done += kb;
+    }
+    if (cur == 1) TVS_HIP_TRY(launch_copy(grid, p->scratch, pr.bytes(), st));
+    return TVS_OK;
 }
 
 const char* stencil_last_error(void) { return last_error(); }

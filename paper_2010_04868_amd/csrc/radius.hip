@@ -52,9 +52,11 @@ __device__ __forceinline__ int64_t wrap64(int64_t i, int64_t n) {
     return i < 0 ? i + n : (i >= n ? i - n : i);
 }
 
-template <typename T, int D, bool BOX, int R, bool PER>
+// VC: variable coefficients, the weight of offset q at point e is wts[q * N + e]
+template <typename T, int D, bool BOX, int R, bool PER, bool VC = false>
 __global__ __launch_bounds__(256) void plain_r(const T* __restrict__ in, T* __restrict__ out,
-                                               int64_t n0, int64_t n1, int64_t n2, Coeffs<T> cf) {
+                                               int64_t n0, int64_t n1, int64_t n2, Coeffs<T> cf,
+                                               const T* __restrict__ wts = nullptr) {
     using S = StencilR<D, BOX, R>;
     static_assert(S::P <= kMaxPoints, "weights");
     const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -82,7 +84,8 @@ __global__ __launch_bounds__(256) void plain_r(const T* __restrict__ in, T* __re
             const int64_t v = PER ? wrap64(c[a] + S::off(q, a), ext[a]) : c[a] + S::off(q, a);
             at = at * ext[a] + v;
         }
-        acc = term(acc, cf.c[q], in[at], q == 0);
+        const T wq = VC ? wts[(int64_t)q * total + e] : cf.c[q];
+        acc = term(acc, wq, in[at], q == 0);
     });
     out[e] = acc;
 }
@@ -93,18 +96,22 @@ __device__ __forceinline__ double rot_down(double x) { return dpp<kDppWaveShl1>(
 // One segment per wave, four waves per workgroup.  LDS per wave: the
 // segment's input (u[xb-R .. xb+Q+R) at index 0 ..) plus a chunk of slack,
 // then the top level's outputs.
-template <typename T, int R, bool PER>
+// VC: variable coefficients, staged per wave in LDS after the outputs:
+// wb[q * WL + (x - xb)] = wts[q * n + x] for the points the wave computes.
+template <typename T, int R, bool PER, bool VC = false>
 __global__ __launch_bounds__(256) void tstp1d_r(const T* __restrict__ in, T* __restrict__ out,
                                                 int n, int k, int Lv, int nseg, int inlen,
-                                                Coeffs<T> cf) {
+                                                Coeffs<T> cf, const T* __restrict__ wts = nullptr,
+                                                int WL = 0) {
     constexpr int s = R + 1;
     constexpr int WN = 2 * R + 1;
     extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
     const int tid = threadIdx.x, lane = tid & 63;
     const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int sg = (int)blockIdx.x * 4 + w;
-    T* inb = reinterpret_cast<T*>(smem_raw) + (size_t)w * (inlen + Lv);
+    T* inb = reinterpret_cast<T*>(smem_raw) + (size_t)w * (inlen + Lv + (VC ? WN * WL : 0));
     T* obuf = inb + inlen;
+    T* wb = obuf + Lv;
     const bool live = sg < nseg;  // uniform per wave
     const int X0 = sg * Lv;
     const int xb = X0 - (k - 1) * R;               // level 1's first point
@@ -118,6 +125,12 @@ __global__ __launch_bounds__(256) void tstp1d_r(const T* __restrict__ in, T* __r
             else if (x >= 0 && x < n)
                 v = in[x];
             inb[i] = v;
+        }
+    if (VC && live)
+        for (int i = lane; i < WN * WL; i += 64) {
+            const int q = i / WL, x = xb + i % WL;
+            const int xi = PER ? ((x % n) + n) % n : min(max(x, 0), n - 1);
+            wb[i] = wts[(int64_t)q * n + xi];
         }
     __syncthreads();
     if (live) {
@@ -137,10 +150,19 @@ __global__ __launch_bounds__(256) void tstp1d_r(const T* __restrict__ in, T* __r
 #pragma unroll
                 for (int i = 0; i + 1 < WN; ++i) wv[i] = wv[i + 1];
                 wv[WN - 1] = nv;
-                T acc = cf.c[0] * wv[0];
-#pragma unroll
-                for (int i = 1; i < WN; ++i) acc = acc + cf.c[i] * wv[i];
                 const int x = xb + q - s * lane;
+                T acc;
+                if constexpr (VC) {
+                    // lanes still filling the pipeline (x < xb) read any weight
+                    const int o = max(x - xb, 0);
+                    acc = wb[o] * wv[0];
+#pragma unroll
+                    for (int i = 1; i < WN; ++i) acc = acc + wb[i * WL + o] * wv[i];
+                } else {
+                    acc = cf.c[0] * wv[0];
+#pragma unroll
+                    for (int i = 1; i < WN; ++i) acc = acc + cf.c[i] * wv[i];
+                }
                 if (!PER) acc = (x < R || x >= n - R) ? wv[R] : acc;  // fixed ends
                 outv = acc;
                 if (lane == k - 1 && x >= X0 && x < X0 + Lv && x < n) obuf[x - X0] = outv;
@@ -225,7 +247,108 @@ hipError_t tstp1d_radius_t(const Problem& p, const BandGeom& g, const T* in, T* 
     return hipErrorInvalidValue;
 }
 
+// Variable coefficients: plain steps of radius 1..3 in any dimension.
+template <typename T, int D, bool BOX, int R>
+hipError_t plain_vc_go(const Problem& p, const T* in, T* out, const T* wts, hipStream_t st) {
+    const int64_t total = p.elems();
+    const dim3 grid((unsigned)((total + 255) / 256));
+    const Coeffs<T> none{};
+    if (p.boundary == TVS_PERIODIC)
+        hipLaunchKernelGGL((plain_r<T, D, BOX, R, true, true>), grid, dim3(256), 0, st, in, out,
+                           p.dims[0], p.dims[1], p.dims[2], none, wts);
+    else
+        hipLaunchKernelGGL((plain_r<T, D, BOX, R, false, true>), grid, dim3(256), 0, st, in, out,
+                           p.dims[0], p.dims[1], p.dims[2], none, wts);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t plain_vc_t(const Problem& p, const T* in, T* out, const T* wts, hipStream_t st) {
+    const bool box = p.shape == TVS_BOX;
+    const int r = p.radius;
+    if (p.ndim == 1) {
+        if (r == 1) return plain_vc_go<T, 1, false, 1>(p, in, out, wts, st);
+        if (r == 2) return plain_vc_go<T, 1, false, 2>(p, in, out, wts, st);
+        if (r == 3) return plain_vc_go<T, 1, false, 3>(p, in, out, wts, st);
+    } else if (p.ndim == 2) {
+        if (r == 1) return box ? plain_vc_go<T, 2, true, 1>(p, in, out, wts, st)
+                               : plain_vc_go<T, 2, false, 1>(p, in, out, wts, st);
+        if (r == 2) return box ? plain_vc_go<T, 2, true, 2>(p, in, out, wts, st)
+                               : plain_vc_go<T, 2, false, 2>(p, in, out, wts, st);
+        if (r == 3 && !box) return plain_vc_go<T, 2, false, 3>(p, in, out, wts, st);
+    } else {
+        if (r == 1) return box ? plain_vc_go<T, 3, true, 1>(p, in, out, wts, st)
+                               : plain_vc_go<T, 3, false, 1>(p, in, out, wts, st);
+        if (r == 2 && !box) return plain_vc_go<T, 3, false, 2>(p, in, out, wts, st);
+        if (r == 3 && !box) return plain_vc_go<T, 3, false, 3>(p, in, out, wts, st);
+    }
+    return hipErrorInvalidValue;
+}
+
+int vc_wl(int R, int k, int Lv) {
+    const int Q = Lv + (k - 1) * (2 * R + 1);
+    return 64 * ((Q + 63) / 64);  // every step of the last chunk reads inside
+}
+
+template <typename T, int R, bool PER>
+hipError_t tstp1d_vc_go(const Problem& p, int k, int Lv, const T* in, T* out, const T* wts,
+                        hipStream_t st) {
+    const int n = (int)p.dims[0];
+    if (k < 1 || k > 64 || Lv < 1) return hipErrorInvalidValue;
+    const int inlen = tstp1d_r_inlen(R, k, Lv), WL = vc_wl(R, k, Lv);
+    const size_t lds = (size_t)4 * (inlen + Lv + (2 * R + 1) * WL) * sizeof(T);
+    if (lds > 160 * 1024) return hipErrorInvalidValue;
+    static bool attr_set = false;
+    if (!attr_set) {
+        (void)hipFuncSetAttribute((const void*)tstp1d_r<T, R, PER, true>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        attr_set = true;
+    }
+    const int nseg = (n + Lv - 1) / Lv;
+    const Coeffs<T> none{};
+    hipLaunchKernelGGL((tstp1d_r<T, R, PER, true>), dim3((unsigned)((nseg + 3) / 4)), dim3(256),
+                       lds, st, in, out, n, k, Lv, nseg, inlen, none, wts, WL);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t tstp1d_vc_t(const Problem& p, int k, int Lv, const T* in, T* out, const T* wts,
+                       hipStream_t st) {
+    const bool per = p.boundary == TVS_PERIODIC;
+    switch (p.radius) {
+        case 1: return per ? tstp1d_vc_go<T, 1, true>(p, k, Lv, in, out, wts, st)
+                           : tstp1d_vc_go<T, 1, false>(p, k, Lv, in, out, wts, st);
+        case 2: return per ? tstp1d_vc_go<T, 2, true>(p, k, Lv, in, out, wts, st)
+                           : tstp1d_vc_go<T, 2, false>(p, k, Lv, in, out, wts, st);
+        case 3: return per ? tstp1d_vc_go<T, 3, true>(p, k, Lv, in, out, wts, st)
+                           : tstp1d_vc_go<T, 3, false>(p, k, Lv, in, out, wts, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
 }  // namespace
+
+size_t tstp1d_vc_lds_bytes(const Problem& p, int k, int Lv) {
+    const int R = p.radius;
+    return (size_t)4 * (tstp1d_r_inlen(R, k, Lv) + Lv + (2 * R + 1) * vc_wl(R, k, Lv)) *
+           p.elem_bytes();
+}
+
+hipError_t launch_plain_varcoef(const Problem& p, const void* in, void* out, const void* wts,
+                                hipStream_t st) {
+    if (p.dtype == TVS_F64)
+        return plain_vc_t<double>(p, (const double*)in, (double*)out, (const double*)wts, st);
+    return plain_vc_t<float>(p, (const float*)in, (float*)out, (const float*)wts, st);
+}
+
+hipError_t launch_tstp1d_varcoef(const Problem& p, int k, int Lv, const void* in, void* out,
+                                 const void* wts, hipStream_t st) {
+    if (p.ndim != 1) return hipErrorInvalidValue;
+    if (p.dtype == TVS_F64)
+        return tstp1d_vc_t<double>(p, k, Lv, (const double*)in, (double*)out, (const double*)wts,
+                                   st);
+    return tstp1d_vc_t<float>(p, k, Lv, (const float*)in, (float*)out, (const float*)wts, st);
+}
 
 // Which (ndim, shape, radius > 1) combinations have kernels: weights of at
 // most kMaxPoints points.

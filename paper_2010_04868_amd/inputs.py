@@ -144,6 +144,22 @@ def star1d5p(n: int = 100000, T: int = 1000) -> Problem:
                    (0.05, 0.2, 0.5, 0.2, 0.05), T, 11)
 
 
+def vc1d3p(n: int = 100000, T: int = 1000) -> Problem:
+    """1D 3-point Jacobi with variable coefficients (a heat equation with a
+    diffusivity per point): weights (a(x), 1 - 2a(x), a(x)), a(x) uniform in
+    [0.1, 0.4] from varcoef_weights; fixed ends.  ``coeffs`` is empty: the
+    weights are an array."""
+    return Problem("vc1d3p", (n,), F64, STAR, 3, JACOBI, DIRICHLET, (), T, 12)
+
+
+def varcoef_weights(p: Problem) -> np.ndarray:
+    """Weights of shape (3, n) for vc1d3p, drawn after the grid from
+    PCG64((seed, 1))."""
+    rng = np.random.Generator(np.random.PCG64((p.seed, 1)))
+    a = rng.uniform(0.1, 0.4, size=p.dims[0])
+    return np.stack([a, 1.0 - 2.0 * a, a]).astype(_NP[p.dtype])
+
+
 def gs1d3p(n: int = 100000, T: int = 1000) -> Problem:
     """1D 3-point Gauss-Seidel in place, coefficients (1/4, 1/2, 1/4), fixed ends."""
     return Problem("gs1d3p", (n,), F64, STAR, 3, GAUSS_SEIDEL, DIRICHLET, (0.25, 0.5, 0.25), T, 6)

@@ -107,6 +107,19 @@ def test_huge_plane_runs_plain():
                                     tuning="method=tstp,k=2,w=64,h=32,c=8")) == E["TVS_E_INVALID"]
 
 
+def test_varcoef_argument_errors_without_device():
+    lib = _lib.load()
+    fake = ctypes.c_void_p(0x1000)
+    p = tvs.Plan((16, 16), F64, STAR, 5)
+    assert lib.stencil_run_varcoef(p.handle, fake, None, 3, None) == E["TVS_E_INVALID"]
+    assert lib.stencil_run_varcoef(p.handle, fake, fake, -1, None) == E["TVS_E_INVALID"]
+    assert lib.stencil_run_varcoef(p.handle, fake, fake, 0, None) == 0
+    gs = tvs.Plan((16, 16), F64, STAR, 5, GAUSS_SEIDEL)
+    assert lib.stencil_run_varcoef(gs.handle, fake, fake, 3, None) == E["TVS_E_UNSUPPORTED"]
+    life = tvs.LifePlan((16, 16))
+    assert lib.stencil_run_varcoef(life.handle, fake, fake, 3, None) == E["TVS_E_INVALID"]
+
+
 def test_radius_plans_without_device():
     p = tvs.Plan((1000,), F64, STAR, 5)              # radius 2: the 1D pipeline, skew 3
     inf = p.info()
