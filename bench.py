@@ -442,8 +442,9 @@ def main():
     ap.add_argument("--T", type=int, default=None, help="time steps (default: the workload's)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU; runs on several GPUs are not part of this build "
-              "(how the sweep would shard is described in DESIGN.md)", file=sys.stderr)
+        print("bench.py measures one GPU: --gpus N with N > 1 is not supported (the sweep runs "
+              "on a single device; a larger grid would be split into slabs along axis 0, one "
+              "per GPU, exchanging k-deep halos per band)", file=sys.stderr)
         sys.exit(2)
 
     import torch
