@@ -31,6 +31,8 @@
 // at consecutive addresses.  Entries whose k falls outside the grid are never
 // read.  The layout takes (wi + wj + 1) times the grid's memory plus the
 // border planes: 3x for the star, 7x for the box.
+#include <algorithm>
+
 #include "kernels.hpp"
 
 namespace tvs {
@@ -74,18 +76,22 @@ __global__ __launch_bounds__(256) void gs3d_layout(T* grid, T* lay, Gs3dGeom g) 
 
 template <typename T, bool BOX>
 __global__ __launch_bounds__(256) void gs3d_planes(T* lay, Gs3dGeom g, Coeffs<T> cf, int L,
-                                                   int G, int dmin, int dmax) {
+                                                   int G, int dmin, int dmax, int jblocks) {
     using S = Stencil<3, BOX>;
     constexpr int WI = BOX ? 4 : 1, WJ = BOX ? 2 : 1;
     // blocks: sweep slot fastest (slots G planes apart share rows of the
     // planes between them, so they run together and meet in L2), then
     // column blocks; blockIdx.y is the row
-    const int K = (int)gridDim.x / ((g.n1 - 2 + 255) / 256);
+    const int K = (int)gridDim.x / jblocks;
     const int slot = (int)blockIdx.x % K, jb = (int)blockIdx.x / K;
     const int d = dmin + L - G * slot;  // slot s: the s-th oldest sweep of the group
     if (d < dmin || d > dmax) return;   // uniform per workgroup
     const int i = 1 + (int)blockIdx.y;
-    const int j = 1 + jb * 256 + (int)threadIdx.x;
+    // row i of plane d holds the points with k = d - WI*i - WJ*j in 1..n2-2:
+    // threads start at the first such j (ceil((d - WI*i - (n2-2)) / WJ), at least 1)
+    const int num = d - WI * i - (g.n2 - 2);
+    const int jlo = max(1, num <= 0 ? -((-num) / WJ) : (num + WJ - 1) / WJ);
+    const int j = jlo + jb * 256 + (int)threadIdx.x;
     const int k = d - WI * i - WJ * j;
     if (j > g.n1 - 2 || k < 1 || k > g.n2 - 2) return;
     const int64_t rowp = g.n1, planep = (int64_t)g.n0 * g.n1;
@@ -110,15 +116,18 @@ hipError_t launch_gs3d_t(const Problem& p, T* lay, const Coeffs<T>& cf, int swee
     const int G = box ? 8 : 2;
     const int dmin = g.wi + g.wj + 1;  // interior planes
     const int dmax = g.wi * (g.n0 - 2) + g.wj * (g.n1 - 2) + (g.n2 - 2);
-    const dim3 grid((unsigned)(sweeps * ((g.n1 - 2 + 255) / 256)), (unsigned)(g.n0 - 2));
+    // points per (plane, row): at most n2-2 (star) or ceil((n2-2)/2) (box), and at most n1-2
+    const int jspan = std::min(g.n1 - 2, box ? (g.n2 - 2 + 1) / 2 : g.n2 - 2);
+    const int jblocks = (jspan + 255) / 256;
+    const dim3 grid((unsigned)(sweeps * jblocks), (unsigned)(g.n0 - 2));
     const int launches = (dmax - dmin + 1) + G * (sweeps - 1);
     for (int L = 0; L < launches; ++L) {
         if (box)
             hipLaunchKernelGGL((gs3d_planes<T, true>), grid, dim3(256), 0, st, lay, g, cf, L, G,
-                               dmin, dmax);
+                               dmin, dmax, jblocks);
         else
             hipLaunchKernelGGL((gs3d_planes<T, false>), grid, dim3(256), 0, st, lay, g, cf, L, G,
-                               dmin, dmax);
+                               dmin, dmax, jblocks);
     }
     return hipGetLastError();
 }
