@@ -234,7 +234,7 @@ typedef struct tvs_lcs tvs_lcs;
 
 /* Plan a run for lengths m, n (each 0 .. 2^31-256).  tuning: NULL, or
  * comma-separated "w=W" (tile width in columns, a multiple of 64 in 64..4096,
- * default 512) and "r=R" (tile height in rows, a multiple of 64 in 64..1024,
+ * default 1024) and "r=R" (tile height in rows, a multiple of 64 in 64..1024,
  * default 256: one wave per 64 rows); (R/64 + 1) x (W + 192) int32 values
  * must fit 160 KiB of LDS.  No device call; a corner array of ceil(n/W)
  * int32 values is allocated at the first run. */

@@ -36,12 +36,13 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <type_traits>
 
 #include "kernels.hpp"
 
 struct tvs_lcs {
     int64_t m = 0, n = 0;
-    int tw = 512;    // tile columns
+    int tw = 1024;   // tile columns
     int rows = 256;  // tile rows: 64 per wave
     int nI = 0, nJ = 0;
     int32_t* corner = nullptr;
@@ -119,6 +120,7 @@ __global__ __launch_bounds__(1024) void lcs_diag(const uint8_t* __restrict__ a,
     // a delay-line lane takes max(north, INT_MIN) = north at every step
     const int32_t cap = vrow ? INT32_MAX : INT32_MIN;
     const unsigned span = vrow ? (unsigned)twt : 0xffffffffu;
+    const bool full_tile = x0 + 64 * W - 1 <= m;  // uniform
     __syncthreads();
     int32_t out = west0;                // this row's latest value
     int32_t nw = lane_shift(out, cor);  // lcs[x-1][y0-1] for the first column
@@ -134,18 +136,41 @@ __global__ __launch_bounds__(1024) void lcs_diag(const uint8_t* __restrict__ a,
             // lane 0 takes step mm's pair after mm rotations
             int32_t tin = src[q0 + lane], bin = bv[q0 + lane];
             int32_t obot = 0;  // lane 63's outputs of this chunk, oldest in lane 0
-            static_for<0, 64>([&](auto mc) {
-                constexpr int mm = decltype(mc)::value;
-                const int32_t N = lane_shift(out, tin);  // lcs[x-1][y]
-                bq = lane_shift(bq, bin);                 // B[y]
-                tin = lane_rotate_down(tin);
-                bin = lane_rotate_down(bin);
-                const int32_t f = bq == ax ? nw + 1 : max(N, min(out, cap));
-                const bool valid = (unsigned)(q0 + mm - lane) < span;
-                out = valid ? f : out;
-                nw = N;
-                obot = dpp32<kDppWaveShl1>(out, obot);  // lane 63 <- its own output
-            });
+            // CHECK: lanes may be outside their column range at some step of
+            // the chunk (the first chunk, and chunks reaching past the tile's
+            // last column); in the others every lane computes at every step
+            // FULL: every row of the tile exists (all but the last band), so
+            // no lane is a delay line and the west value needs no cap
+            auto chunk = [&](auto check, auto full) {
+                static_for<0, 64>([&](auto mc) {
+                    constexpr int mm = decltype(mc)::value;
+                    // rotate first: the shifts below then consume tin and bin
+                    const int32_t tnext = lane_rotate_down(tin);
+                    const int32_t bnext = lane_rotate_down(bin);
+                    const int32_t N = lane_shift(out, tin);  // lcs[x-1][y]
+                    bq = lane_shift(bq, bin);                 // B[y]
+                    tin = tnext;
+                    bin = bnext;
+                    const int32_t west = decltype(full)::value ? out : min(out, cap);
+                    const int32_t f = bq == ax ? nw + 1 : max(N, west);
+                    if constexpr (decltype(check)::value) {
+                        const bool valid = (unsigned)(q0 + mm - lane) < span;
+                        out = valid ? f : out;
+                    } else {
+                        out = f;
+                    }
+                    nw = N;
+                    obot = dpp32<kDppWaveShl1>(out, obot);  // lane 63 <- its own output
+                });
+            };
+            const bool inner = q0 >= 64 && q0 + 64 <= twt;
+            if (full_tile) {
+                if (inner) chunk(std::false_type{}, std::true_type{});
+                else chunk(std::true_type{}, std::true_type{});
+            } else {
+                if (inner) chunk(std::false_type{}, std::false_type{});
+                else chunk(std::true_type{}, std::false_type{});
+            }
             // lane i holds column q0 + i - 63 of this wave's bottom row
             const int yc = q0 + lane - 63;
             if (dst) {
@@ -201,8 +226,8 @@ int stencil_lcs_plan(tvs_lcs** out, int64_t m, int64_t n, const char* tuning) {
     if (m < 0 || n < 0 || m > kMax || n > kMax)
         return set_error(TVS_E_SHAPE, "sequence lengths must lie in 0..2^31-256");
     // measured on 200000 x 200000 over widths 128..2048 and heights 64..1024:
-    // 512 x 256 best (806 GCells/s), within a few percent of 256 x 64
-    int tw = 512, rows = 256;
+    // 1024 x 256 best (1012 GCells/s; 512 x 256: 906, 1024 x 512: 921)
+    int tw = 1024, rows = 256;
     int rc = parse_lcs_tuning(tuning, &tw, &rows);
     if (rc) return rc;
     if (lcs_lds_bytes(tw, rows) > 160 * 1024)

@@ -175,9 +175,9 @@ def test_life_plans_without_device():
 def test_lcs_plans_without_device():
     lib = _lib.load()
     p = tvs.LcsPlan(200000, 1000)
-    assert p.tile_width == 512 and p.tile_rows == 256
+    assert p.tile_width == 1024 and p.tile_rows == 256
     assert tvs.LcsPlan(10, 10, "w=1024").tile_width == 1024
-    assert tvs.LcsPlan(0, 0).tile_width == 512
+    assert tvs.LcsPlan(0, 0).tile_width == 1024
     assert tvs.LcsPlan(10, 10, "w=512,r=1024").tile_rows == 1024
     assert tvs.LcsPlan(10, 10, "w=64").tile_rows == 256
     for bad in ("w=100", "w=32", "w=8192", "k=4", "w=", "r=32", "r=2048", "w=4096,r=1024"):
