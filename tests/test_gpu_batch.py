@@ -27,6 +27,7 @@ MEMBERS = [
     ((129, 130), BOX, JACOBI, DIRICHLET, F64, 17, "uni"),   # same variant as #2
     ((500,), STAR, GAUSS_SEIDEL, DIRICHLET, F64, 11, "rand"),  # 1D Gauss-Seidel
     ((131, 600), BOX, GAUSS_SEIDEL, DIRICHLET, F32, 5, "uni"),  # several on side streams
+    ((17, 20, 23), BOX, GAUSS_SEIDEL, DIRICHLET, F64, 4, "rand"),  # 3D Gauss-Seidel
 ]
 
 
