@@ -71,8 +71,10 @@ __global__ void lcs_init(int32_t* row, int32_t* col, int32_t* corner, int m, int
 __device__ __forceinline__ int32_t lane_shift(int32_t x, int32_t first) {
     return dpp32<kDppWaveShr1>(first, x);  // lane i <- lane i-1; lane 0 <- first
 }
+// lane i <- lane i+1; lane 63 reads 0 (bound_ctrl), so the move needs no old
+// value and the compiler no copy of it
 __device__ __forceinline__ int32_t lane_rotate_down(int32_t x) {
-    return dpp32<kDppWaveShl1>(x, x);  // lane i <- lane i+1 (lane 63 keeps its value)
+    return __builtin_amdgcn_update_dpp(0, x, kDppWaveShl1, 0xF, 0xF, true);
 }
 
 // The tiles of anti-diagonal d, one workgroup of W = blockDim.x / 64 waves
