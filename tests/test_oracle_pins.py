@@ -238,6 +238,45 @@ def test_no_fused_multiply_add():
     assert exact_product != 1 and float(exact_product) == 1.0
 
 
+# The FP32 mirror must follow the same order and rounding in single
+# precision: every product and sum rounded to float32 on its own.  These
+# inputs give a different float32 result if the mirror accumulated in double
+# (or any wider type), reassociated, or fused a multiply and an add.
+
+def test_left_to_right_summation_f32():
+    # 1 + 1e8 rounds to 1e8 in float32 (the spacing there is 8), and 1e8 - 1e8
+    # is 0.  Accumulating in double keeps 100000001 and ends at 1; summing in
+    # another order also gives 1.
+    assert np.float32(1.0) + np.float32(1e8) == np.float32(1e8)
+    u = np.array([0.0, 1.0, 1e8, -1e8, 0.0], np.float32)
+    got = oracle.sweep(u, [1.0, 1.0, 1.0], STAR, JACOBI, DIRICHLET, 1, precision="f32")
+    assert got.dtype == np.float32 and got[2] == 0.0
+    # the first term enters as a product: -0.0 survives only without a +0 start
+    u = np.array([-0.0, -1.0, -5.0, 0.0], np.float32)
+    got = oracle.sweep(u, [1.0, 0.0, 0.0], STAR, JACOBI, DIRICHLET, 1, precision="f32")
+    assert got[1] == 0.0 and math.copysign(1.0, float(got[1])) == -1.0
+
+
+def test_no_fused_multiply_add_f32():
+    # float32(1/3) = 11184811 * 2**-25, so 3 * float32(1/3) = 1 + 2**-25
+    # exactly; rounded to float32 (spacing 2**-23 at 1) it is 1.0, and
+    # -1 + 1.0 = 0.  A fused multiply-add, or a product kept in double, leaves
+    # 2**-25 instead.
+    third = np.float32(1.0) / np.float32(3.0)
+    exact = Fraction(3) * Fraction(float(third))
+    assert exact == 1 + Fraction(1, 2**25) and np.float32(3.0) * third == np.float32(1.0)
+    u = np.array([0.0, -1.0, third, 7.0], np.float32)
+    got = oracle.sweep(u, [1.0, 3.0, 0.0], STAR, JACOBI, DIRICHLET, 1, precision="f32")
+    assert got[2] == 0.0
+    # the weights themselves are rounded to float32 first (nearest even):
+    # 0.1 becomes 13421773 * 2**-27, and 0.1f * 10 rounds to exactly 1.0f
+    u = np.array([0.0, 10.0, 0.0], np.float32)
+    got = oracle.sweep(u, [0.0, 0.1, 0.0], STAR, JACOBI, DIRICHLET, 1, precision="f32")
+    w = Fraction(13421773, 2**27)
+    assert float(np.float32(0.1)) == float(w)
+    assert got[1] == np.float32(float(w * 10))
+
+
 # ---------------------------------------------------------------------------
 # closed forms
 # ---------------------------------------------------------------------------
@@ -480,6 +519,56 @@ def test_life_block_survives_and_grows_its_edges():
     edges = [(3, 4), (3, 5), (6, 4), (6, 5), (4, 3), (5, 3), (4, 6), (5, 6)]
     got = oracle.life(_board((10, 10), block), DIRICHLET, 1)
     assert np.array_equal(got, _board((10, 10), block + edges))
+
+
+def test_life_l_tromino_corner_stays_dead_and_cells_survive_with_two():
+    # live A(4,4), B(4,5), C(5,4).  Each live cell sees the other two (2:
+    # survives).  The empty corner (5,5) of their 2x2 box sees all three (3:
+    # a dead cell with 3 stays dead under B2).  (3,4), (3,5) see A and B, and
+    # (4,3), (5,3) see A and C (2: born).  Every other cell sees at most 1.
+    got = oracle.life(_board((10, 10), [(4, 4), (4, 5), (5, 4)]), DIRICHLET, 1)
+    want = _board((10, 10), [(4, 4), (4, 5), (5, 4), (3, 4), (3, 5), (4, 3), (5, 3)])
+    assert np.array_equal(got, want)
+
+
+def test_life_blinker_middle_survives_with_two():
+    # row (4,3), (4,4), (4,5).  The middle sees 2 (survives); the ends see 1
+    # (die).  (3,4) and (5,4) see all three (3: stay dead).  The four diagonal
+    # cells (3,3), (3,5), (5,3), (5,5) see 2 each (born); the rest see <= 1.
+    got = oracle.life(_board((9, 9), [(4, 3), (4, 4), (4, 5)]), DIRICHLET, 1)
+    want = _board((9, 9), [(4, 4), (3, 3), (3, 5), (5, 3), (5, 5)])
+    assert np.array_equal(got, want)
+
+
+def test_life_plus_centre_dies_with_four():
+    # centre (4,4) and its four edge neighbours.  The centre sees 4 (dies); each
+    # arm sees the centre and the two arms beside it (3: survives); the four
+    # diagonal corners see 3 (stay dead); every other cell sees at most 1.
+    arms = [(3, 4), (5, 4), (4, 3), (4, 5)]
+    got = oracle.life(_board((9, 9), arms + [(4, 4)]), DIRICHLET, 1)
+    assert np.array_equal(got, _board((9, 9), arms))
+
+
+def test_life_full_square_and_square_less_a_corner():
+    # full 3x3 square, rows and columns 3..5.  Centre sees 8 and the edge
+    # middles 5 (die); corners see 3 (survive).  Outside, the cells beside an
+    # edge middle, e.g. (2,4), see 3 (stay dead); (2,3), (2,5), (3,2), (5,2),
+    # (6,3), (6,5), (3,6), (5,6) see 2 (born); (2,2)-type corners see 1.
+    sq = [(i, j) for i in range(3, 6) for j in range(3, 6)]
+    got = oracle.life(_board((9, 9), sq), DIRICHLET, 1)
+    corners = [(3, 3), (3, 5), (5, 3), (5, 5)]
+    born = [(2, 3), (2, 5), (3, 2), (5, 2), (6, 3), (6, 5), (3, 6), (5, 6)]
+    assert np.array_equal(got, _board((9, 9), corners + born))
+    # the same square without (5,5): the centre sees 7, (4,5) and (5,4) see 4,
+    # (3,4) and (4,3) see 5 (all die); corners (3,3), (3,5), (5,3) see 3
+    # (survive); (5,5) sees 3 (stays dead); outside, (2,3), (2,5), (3,2),
+    # (5,2), (3,6), (6,3), (4,6) and (6,4) see 2 (born), (2,4) and (4,2) see
+    # 3 (stay dead), (5,6) and (6,5) see 1.
+    sq7 = [c for c in sq if c != (5, 5)]
+    got = oracle.life(_board((9, 9), sq7), DIRICHLET, 1)
+    want = [(3, 3), (3, 5), (5, 3), (2, 3), (2, 5), (3, 2), (5, 2), (3, 6), (6, 3), (4, 6),
+            (6, 4)]
+    assert np.array_equal(got, _board((9, 9), want))
 
 
 def test_life_full_torus_dies():
