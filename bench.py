@@ -28,13 +28,22 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
-# FP64 vector: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.3e12 separately
-# issued multiplies or adds per second (the 78.6 TFLOP/s figure counts an FMA
-# as two; the bit-exact update uses no FMA).  FP32 vector: twice that with
-# packed two-wide instructions (the 157.3 TFLOP/s figure), which the library
-# is built without, so its FP32 kernels can issue at most the FP64 rate.
+# Vector ALU issue ceiling: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.3e12
+# separately issued lane operations per second.  The published FP64 vector
+# figure (78.6 TFLOP/s) counts a fused multiply-add as two; the bit-exact
+# update issues every multiply and add on its own, so 39.3 T is its ceiling.
+# FP32 reaches 157.3 TFLOP/s only with packed two-wide FMAs; the library is
+# built without packed FP32, so its FP32 (and int32) kernels have the same
+# 39.3 T ceiling.
 ALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
-ALU_PEAK_TOPS_F32 = 2 * ALU_PEAK_TOPS
+PUBLISHED_VECTOR_TFLOPS = {"f64": 78.6, "f32": 157.3, "i32": 78.6}
+# The paper's own measurements, for context (Section 4.1: two 12-core Xeon
+# E5-2670 at 2.7 GHz, AVX2 256-bit vectors, ICC -O3 -xHost; Section 4.2).  It
+# prints almost no absolute rates; its figures are relative.
+PAPER_CONTEXT = ("paper (2x 12-core Xeon E5-2670, 2.7 GHz, AVX2): scalar Gauss-Seidel about "
+                 "0.4 Gstencil/s for every GS stencil; temporal vectorization 3x scalar and "
+                 "1.6x compiler auto-vectorization on Heat-1D at every core count; GS-2D 2.2x "
+                 "scalar on 24 cores; LCS 5.3x scalar on 24 cores (Section 4.2)")
 METRIC = "GStencil/s + % HBM roofline vs plain sweep; p50/p99 latency mixed load"
 # workload -> (rocprof summary of its band kernel, the sources that kernel is built from)
 PROFILES = {
@@ -59,9 +68,9 @@ def kernel_hash(workload: str = "box2d9p") -> str:
     return h.hexdigest()[:16]
 
 
-def profiled_traffic(workload: str):
+def profiled_traffic(workload: str, schedule: str):
     """HBM bytes per band launch from the committed rocprof summary, if it was
-    taken on the current kernel sources (else None)."""
+    taken on the current kernel sources and on this schedule (else None)."""
     if workload not in PROFILES:
         return None
     try:
@@ -70,9 +79,65 @@ def profiled_traffic(workload: str):
         return None
     m = re.search(r"kernel sources hash: `([0-9a-f]+)`", text)
     t = re.search(r"HBM traffic per band launch \(bytes\): `([0-9.eE+]+)`", text)
-    if not m or not t or m.group(1) != kernel_hash(workload):
+    s = re.search(r"profiled schedule: `([^`]+)`", text)
+    if not m or not t or not s or m.group(1) != kernel_hash(workload) or s.group(1) != schedule:
         return None
     return float(t.group(1))
+
+
+def _tile_ranges(n, valid, ext, k, periodic):
+    """Tiles along one axis and the interior range [lo, hi) of tiles that
+    touch no fixed border (the band kernel's own test)."""
+    nt = -(-n // valid)
+    if periodic:
+        return nt, 0, nt
+    inner = [t for t in range(nt) if t * valid - k > 0 and t * valid - k + ext - 1 < n - 1]
+    return (nt, inner[0], inner[-1] + 1) if inner else (nt, 0, 0)
+
+
+def band_work(p, info, inputs, uniform):
+    """(computed point updates, executed arithmetic ops) of one band launch of
+    the 2D/3D band kernel.  A workgroup computes every point of its tile
+    (halo columns included) at every level; an interior tile runs whole
+    groups of 4 steps, Lin + k + 1 rounded up (its lanes compute outside the
+    trapezoid too, with no test), a border tile computes only the Lin stream
+    rows of each level.  Per computed point: P - 1 sums, and P products --
+    or, in interior tiles with equal weights, each value's product once:
+    (C + 2) / C per point in 2D; in 3D (C + 2) / C per stencil row of the
+    box and (C + 2 + 2C) / C in all for the star."""
+    k, W, H, Lv, C = info["k"], info["tile_w"], info["tile_h"], info["tile_l"], info["lane_c"]
+    per = p.boundary == inputs.PERIODIC
+    D, P = p.ndim, p.order
+    Lin = Lv + 2 * k
+    Q = -(-(Lin + k + 1) // 4) * 4
+    nz, nx = p.dims[0], p.dims[-1]
+    ntx, x0, x1 = _tile_ranges(nx, W - 2 * k, W, k, per)
+    nts, s0, s1 = _tile_ranges(nz, Lv, Lin, k, per)
+    if D == 3:
+        nty, y0, y1 = _tile_ranges(p.dims[1], H - 2 * k, H, k, per)
+    else:
+        nty, y0, y1 = 1, 0, 1
+    n_int = (x1 - x0) * (y1 - y0) * (s1 - s0)
+    n_all = ntx * nty * nts
+    if not per and (x1 <= x0 or y1 <= y0 or s1 <= s0):
+        n_int = 0
+    pts = W * (H if D == 3 else 1)
+    upd_int = n_int * k * pts * Q
+    upd_bdr = (n_all - n_int) * k * pts * Lin
+    full = (P - 1) + P
+    if uniform and p.dtype != inputs.I32:
+        if D == 2:
+            prods = (C + 2) / C
+        elif p.shape == inputs.BOX:
+            prods = 3 * (C + 2) / C
+        else:
+            prods = (C + 2 + 2 * C) / C
+        shared = (P - 1) + prods
+    elif p.dtype == inputs.I32:
+        full = shared = LIFE_EXEC_OPS
+    else:
+        shared = full
+    return upd_int + upd_bdr, upd_int * shared + upd_bdr * full
 
 
 # name -> (builder, description); builders take (n, T) overrides or None
@@ -98,10 +163,10 @@ WORKLOADS = {
 # west, and the select between the two.
 LCS_OPS = 4
 
-# Integer operations of one Life update by its definition: 7 additions for
-# the sum of 8 neighbours, and the rule (two equality tests, a non-zero test,
-# an and, an or).
-LIFE_OPS = 12
+# Integer operations of one Life update as the band kernel executes it: 8
+# additions (the running sums of 9 values), the centre's subtraction, 3
+# compares and a select.
+LIFE_EXEC_OPS = 13
 
 
 def _kw(n, T):
@@ -152,7 +217,17 @@ def kernel_name(p, info, inputs) -> str:
         return {1: "gs1d sweep pipeline", 2: "gs2d wavefront", 3: "gs3d_planes"}[p.ndim]
     if p.ndim == 1:
         return "tstp1d_r" if info.get("radius", 1) > 1 else "tstp1d"
-    return "tstp_reg2d" if info.get("kern", 0) == 1 else "tstp_nd"
+    return "tstp_nd"
+
+
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def cpu_baseline(p, budget_s=15.0):
@@ -174,7 +249,7 @@ def cpu_baseline(p, budget_s=15.0):
     sweep(u, steps)
     dt = time.perf_counter() - t0
     return {"value": round(p.updated_points() * steps / dt / 1e9, 4), "unit": "GStencil/s",
-            "cores": 1, "kind": "oracle",
+            "cores": 1, "kind": "oracle", "cpu": cpu_model(),
             "sample": f"{describe(p, inputs)}: {steps} of {p.T} steps, single thread, "
                       f"{dt:.1f} s"}
 
@@ -359,7 +434,7 @@ def lcs_bench(torch, tvs, inputs, args, copy_gbs):
         oracle.lcs(a[:rows], b)
         dt = time.perf_counter() - t0
         out["cpu_baseline"] = {"value": round(rows * p.n / dt / 1e9, 4), "unit": "GCells/s",
-                               "cores": 1, "kind": "oracle",
+                               "cores": 1, "kind": "oracle", "cpu": cpu_model(),
                                "sample": f"the first {rows} rows of the table ({rows} x {p.n}), "
                                          f"single thread, {dt:.1f} s"}
     return out
@@ -420,7 +495,7 @@ def varcoef_bench(torch, tvs, inputs, args, copy_gbs):
         oracle.sweep_varcoef(u0, W, p.shape, p.boundary, steps, p.order)
         dt = time.perf_counter() - t0
         out["cpu_baseline"] = {"value": round(nu * steps / dt / 1e9, 4), "unit": "GStencil/s",
-                               "cores": 1, "kind": "oracle",
+                               "cores": 1, "kind": "oracle", "cpu": cpu_model(),
                                "sample": f"{steps} of {p.T} steps of the same grid, single thread, "
                                          f"{dt:.1f} s"}
     return out
@@ -447,6 +522,7 @@ def main():
               "per GPU, exchanging k-deep halos per band)", file=sys.stderr)
         sys.exit(2)
 
+    import numpy as np
     import torch
 
     import paper_2010_04868_amd as tvs
@@ -516,13 +592,27 @@ def main():
     else:
         band_ms = time_runs(torch, lambda: plan.run(grid, p.coeffs, 2 * k), 10) / 2
         band_updates = nu * k
-    # weighted: P products + (P-1) sums per update; Life: integer operations
-    flops = band_updates * (LIFE_OPS if life else 2 * p.order - 1)
-    achieved_tops = flops / (band_ms / 1e3) / 1e12
+    # the arithmetic the band kernel executes: the 2D/3D band kernel counts
+    # its redundant halo and pipeline-fill work and its shared products
+    # (band_work); the other kernels count P products + (P - 1) sums per
+    # update (Life: its integer operations)
+    nd_band = info["method"] == 1 and p.ndim >= 2 and p.dependence == inputs.JACOBI
+    if nd_band:
+        uniform = len({np.float64(c).tobytes() for c in p.coeffs}) == 1
+        computed, exec_ops = band_work(p, info, inputs, uniform)
+        ops_note = (f"executed: {computed / band_updates:.3f} computed points per update "
+                    f"(trapezoid halo and pipeline fill) x "
+                    f"{exec_ops / computed:.3f} ops per computed point "
+                    f"({'shared products, ' if uniform and not life else ''}no FMA)")
+    else:
+        exec_ops = band_updates * (LIFE_EXEC_OPS if life else 2 * p.order - 1)
+        ops_note = ("executed: " + ("13 integer ops" if life else f"{2 * p.order - 1} ops "
+                    f"({p.order} products + {p.order - 1} sums)") + " per update")
+    achieved_tops = exec_ops / (band_ms / 1e3) / 1e12
     alg_bytes = 2 * eb * band_updates / k            # each point read and written once per band
     achieved_gbs = alg_bytes / (band_ms / 1e3) / 1e9
-    log(f"band kernel: {band_ms:.4f} ms, {achieved_tops:.2f} TFLOP/s algorithmic, "
-        f"{achieved_gbs:.0f} GB/s algorithmic")
+    log(f"band kernel: {band_ms:.4f} ms, {achieved_tops:.2f} T ops/s executed "
+        f"({ops_note}), {achieved_gbs:.0f} GB/s algorithmic")
 
     # plain one-step-per-launch sweep on the same grid
     plain = tvs.Plan.for_problem(p, "method=plain")
@@ -536,9 +626,9 @@ def main():
     del grid
     torch.cuda.empty_cache()
 
-    # int32 has no packed two-wide adds: the unpacked rate, as for FP64
-    peak = ALU_PEAK_TOPS if eb == 8 or life else ALU_PEAK_TOPS_F32
-    traffic = profiled_traffic(args.workload) if args.n is None and args.T is None else None
+    dt_name = "i32" if life else ("f64" if eb == 8 else "f32")
+    traffic = (profiled_traffic(args.workload, plan.tuning())
+               if args.n is None and args.T is None else None)
     out = {
         "metric": METRIC,
         "value": round(value, 2),
@@ -550,7 +640,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "i32" if life else ("f64" if eb == 8 else "f32"),
+        "dtype": dt_name,
         "data": (f"synthetic: 0/1 board, cells live w.p. 1/2, PCG64(seed {p.seed})" if life
                  else f"synthetic: uniform[0,1) PCG64(seed {p.seed})"),
         "config": {"workload": describe(p, inputs),
@@ -563,14 +653,23 @@ def main():
                         "hbm_frac": round(plain_gbs / HBM_PEAK_GBS, 4),
                         "speedup": round(value / plain_value, 3)},
         "roofline": {"bound": "alu", "achieved": round(achieved_tops, 3),
-                     "peak": round(peak, 2), "unit": "TOP/s (int32)" if life else "TFLOP/s",
-                     "frac": round(achieved_tops / peak, 4),
-                     "peak_unpacked": round(ALU_PEAK_TOPS, 2),
+                     "peak": round(ALU_PEAK_TOPS, 2),
+                     "unit": "TOP/s (int32)" if life else "TFLOP/s",
+                     "frac": round(achieved_tops / ALU_PEAK_TOPS, 4),
                      "traffic": traffic,
+                     "ops_counted": ops_note,
+                     "peak_note": "vector issue ceiling for separately issued multiplies and "
+                                  "adds (256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz); published "
+                                  f"vector peak {PUBLISHED_VECTOR_TFLOPS[dt_name]} TFLOP/s "
+                                  "counts FMAs (and packed FP32)",
+                     "frac_of_published": round(achieved_tops /
+                                                PUBLISHED_VECTOR_TFLOPS[dt_name], 4),
+                     "hbm": {"achieved": round(achieved_gbs, 1), "peak": HBM_PEAK_GBS,
+                             "unit": "GB/s", "frac": round(achieved_gbs / HBM_PEAK_GBS, 4),
+                             "algorithmic_bytes": alg_bytes},
                      "kernel": f"{kernel_name(p, info, inputs)} (one launch of k steps)",
-                     "kernel_ms": round(band_ms, 4),
-                     "algorithmic_bytes": alg_bytes,
-                     "algorithmic_GBs": round(achieved_gbs, 1)},
+                     "kernel_ms": round(band_ms, 4)},
+        "paper_context": PAPER_CONTEXT,
     }
     if not args.no_serve and args.workload == "box2d9p":
         t0 = time.perf_counter()

@@ -56,7 +56,7 @@ extern "C" {
 #define TVS_E_INVALID (-1)     /* null pointer, bad enum, T < 0, bad tuning */
 #define TVS_E_SHAPE (-2)       /* ndim not 1..3, an extent < 2r+1, size overflow */
 #define TVS_E_ORDER (-3)       /* point count inconsistent with ndim and shape */
-#define TVS_E_UNSUPPORTED (-4) /* e.g. periodic Gauss-Seidel, radius > 1 */
+#define TVS_E_UNSUPPORTED (-4) /* e.g. periodic Gauss-Seidel, a 3D box of radius > 1 */
 #define TVS_E_NOMEM (-5)       /* device or host allocation failed */
 #define TVS_E_DEVICE (-6)      /* a HIP call failed or a kernel reported abort */
 #define TVS_E_BUSY (-7)        /* server: budget or queue full */
@@ -100,7 +100,7 @@ typedef struct tvs_plan_info {
                           1 = successive levels in successive waves */
     size_t scratch_bytes; /* device memory the plan owns */
     int pl;            /* 1D: lanes per pipeline (16 or 64) */
-    int kern;          /* 2D Jacobi: 0 = LDS level planes, 1 = register pipeline */
+    int kern;          /* kernel kind: always 0 (LDS level planes) */
     char tuning[160];  /* the schedule as a tuning string that stencil_plan accepts */
     int rule;          /* TVS_RULE_WEIGHTED or TVS_RULE_LIFE */
 } tvs_plan_info;
@@ -112,12 +112,14 @@ typedef struct tvs_plan_info {
  *   dtype       TVS_F32 or TVS_F64 (storage and arithmetic precision)
  *   shape       TVS_STAR or TVS_BOX
  *   order       number of stencil points P (star: 2*ndim*r+1, box: (2r+1)^ndim);
- *               r = 1 is supported
+ *               stars of radius 1..3 and boxes of at most 27 points (every
+ *               radius-1 box, the 1D boxes up to radius 3, the 2D radius-2
+ *               box); Gauss-Seidel: radius 1 only
  *   dependence  TVS_JACOBI or TVS_GAUSS_SEIDEL
  *   boundary    TVS_DIRICHLET or TVS_PERIODIC (Gauss-Seidel: Dirichlet only)
  *   tuning      NULL: the tuned default (autotune cache, else a model-based
  *               choice); otherwise "key=value" pairs separated by commas:
- *               method=plain|tstp, k=, s=, w=, h=, l=, c=, lanemap=, pl=, kern=
+ *               method=plain|tstp, k=, s=, w=, h=, l=, c=, lanemap=, pl=, kern=0
  * The plan is created without touching the device; device scratch (the
  * Jacobi second buffer) is allocated at the first run and freed by
  * stencil_plan_destroy.  *out is set only on success.
@@ -141,7 +143,7 @@ int stencil_plan(tvs_plan **out, int ndim, const int64_t *dims, int dtype, int s
  *   dims      2 storage extents, each >= 3
  *   boundary  TVS_DIRICHLET: the outer layer of cells is never written (it
  *             keeps any values it holds); TVS_PERIODIC: indices wrap
- *   tuning    as for stencil_plan (2D Jacobi keys; kern=1 is not available)
+ *   tuning    as for stencil_plan (2D Jacobi keys)
  * The plan has dtype TVS_I32, shape TVS_BOX, order 9, dependence TVS_JACOBI
  * and rule TVS_RULE_LIFE.  stencil_run and stencil_tune take such a plan
  * with coeffs NULL (any coeffs given are ignored); the grid is prod(dims)
@@ -169,8 +171,24 @@ int stencil_plan_destroy(tvs_plan *plan);
  *   T       >= 0; T = 0 enqueues nothing
  *   stream  hipStream_t or NULL
  * One plan runs on one stream at a time; distinct plans may run concurrently.
+ * Gauss-Seidel runs wait for their producers with bounded spins.  A wait that
+ * expires makes that run's result (and that of every later run of the plan,
+ * until it is reported) invalid.  The device work is asynchronous, so the
+ * abort is reported (TVS_E_DEVICE, nothing enqueued) by the first later
+ * stencil_run or stencil_batch_run of the plan that finds the earlier run
+ * complete, or by stencil_plan_check, which waits for it.  Reporting clears
+ * it.
  */
 int stencil_run(tvs_plan *plan, void *grid, const double *coeffs, int64_t T, void *stream);
+
+/*
+ * Wait until the plan's last Gauss-Seidel run has completed and report
+ * whether any of its launches (or of earlier unreported runs) aborted:
+ * TVS_OK, or TVS_E_DEVICE (and the abort is cleared).  Jacobi and Life plans,
+ * and plans that have not run, return TVS_OK at once.  Synchronizes the host
+ * with that run; it enqueues nothing.
+ */
+int stencil_plan_check(tvs_plan *plan);
 
 /*
  * Advance grid by T Jacobi steps of a variable-coefficient stencil: the
@@ -187,7 +205,14 @@ int stencil_run(tvs_plan *plan, void *grid, const double *coeffs, int64_t T, voi
  */
 int stencil_run_varcoef(tvs_plan *plan, void *grid, const void *weights, int64_t T, void *stream);
 
-/* One-call form: plans (through an internal cache keyed by the problem) and runs. */
+/*
+ * One-call form: plans (through an internal cache keyed by the problem and the
+ * current device) and runs; arguments as in stencil_plan and stencil_run.
+ * Calls for the same problem share one cached plan and its scratch: each call
+ * holds the plan while it enqueues, and its stream first waits for the
+ * previous call's work, so calls from several threads or on several streams
+ * are safe (and run one after the other on the device).
+ */
 int stencil_run_simple(void *grid, int ndim, const int64_t *dims, int dtype, const double *coeffs,
                        int shape, int order, int dependence, int boundary, int64_t T,
                        void *stream);
@@ -196,7 +221,8 @@ int stencil_run_simple(void *grid, int ndim, const int64_t *dims, int dtype, con
  * Run n independent problems in persistent launches on one stream.  Each
  * plans[i] must be a Jacobi plan (Gauss-Seidel plans run through their own
  * persistent kernel and are accepted as well); grids[i], coeffs[i], T[i] as
- * in stencil_run.  Every result is bit-identical to stencil_run of the same
+ * in stencil_run.  A plan or a grid may appear at most once among the members
+ * with T[i] > 0 (TVS_E_INVALID): members run at the same time.  Every result is bit-identical to stencil_run of the same
  * problem alone.  The launch sequence is captured once in a hipGraph per
  * distinct batch layout and replayed.
  */
@@ -232,7 +258,7 @@ int stencil_tune(tvs_plan *plan, void *grid, const double *coeffs, int64_t T_pro
  */
 typedef struct tvs_lcs tvs_lcs;
 
-/* Plan a run for lengths m, n (each 0 .. 2^31-256).  tuning: NULL, or
+/* Plan a run for lengths m, n (each 0 .. 2^30).  tuning: NULL, or
  * comma-separated "w=W" (tile width in columns, a multiple of 64 in 64..4096,
  * default 1024) and "r=R" (tile height in rows, a multiple of 64 in 64..1024,
  * default 256: one wave per 64 rows); (R/64 + 1) x (W + 192) int32 values

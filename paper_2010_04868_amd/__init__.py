@@ -119,6 +119,11 @@ class Plan:
                                          ctypes.c_void_p(weights.data_ptr()), int(T),
                                          ctypes.c_void_p(_stream_handle(stream))))
 
+    def check(self) -> None:
+        """Wait for the plan's last run and raise if a Gauss-Seidel launch of it
+        (or of an earlier unreported run) aborted (``stencil_plan_check``)."""
+        check(load().stencil_plan_check(self._h))
+
     def tune(self, grid, coeffs: Optional[Sequence[float]], T_probe: int, stream=None) -> str:
         buf = ctypes.create_string_buffer(256)
         c = None if coeffs is None else _coeff_array(coeffs)

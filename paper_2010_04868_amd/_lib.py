@@ -65,6 +65,7 @@ SIGNATURES = [
     ("stencil_plan_destroy", ctypes.c_int, [vp]),
     ("stencil_run", ctypes.c_int, [vp, vp, dp, i64, vp]),
     ("stencil_run_varcoef", ctypes.c_int, [vp, vp, vp, i64, vp]),
+    ("stencil_plan_check", ctypes.c_int, [vp]),
     ("stencil_run_simple", ctypes.c_int, [vp, ctypes.c_int, ctypes.POINTER(i64), ctypes.c_int,
                                           dp, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                           ctypes.c_int, i64, vp]),

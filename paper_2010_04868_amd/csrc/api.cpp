@@ -4,6 +4,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <string>
 #include <tuple>
@@ -94,13 +95,7 @@ int enqueue_jacobi(tvs_plan* p, void* grid, const CoeffBuf& cb, int64_t T, hipSt
         while (done < T) {
             const int kb = (int)std::min<int64_t>(p->sched.k, T - done);
             BandGeom g = full;
-            Schedule rem = p->sched;
-            if (rem.kern == 1) {  // shallower bands: LDS planes on the same tile width
-                rem.kern = 0;
-                rem.w = 64 * rem.c;
-                rem.lanemap = 1;
-            }
-            if (kb != full.k && !band_geometry(pr, rem, kb, &g)) {
+            if (kb != full.k && !band_geometry(pr, p->sched, kb, &g)) {
                 // a remainder too shallow for the tile shape: plain steps
                 for (int t = 0; t < kb; ++t) {
                     TVS_HIP_TRY(launch_plain_step(pr, buf[cur], buf[1 - cur], cb.bytes, st));
@@ -348,10 +343,14 @@ int stencil_run(tvs_plan* p, void* grid, const double* coeffs, int64_t T, void* 
         bool done = false;
         int rc = run_graph(p, grid, coeffs, T, (hipStream_t)stream, &done);
         if (rc || done) return rc;
+    } else {
+        // an abort of an earlier run is reported (and nothing enqueued)
+        int rc = gs_report_previous(p);
+        if (rc) return rc;
     }
     int rc = enqueue_run(p, grid, coeffs, T, (hipStream_t)stream);
     if (rc) return rc;
-    if (p->prob.dependence == TVS_GAUSS_SEIDEL) return gs_check_status(p, (hipStream_t)stream);
+    if (p->prob.dependence == TVS_GAUSS_SEIDEL) return gs_queue_status_copy(p, (hipStream_t)stream);
     return TVS_OK;
 }
 
@@ -361,28 +360,54 @@ int stencil_run_simple(void* grid, int ndim, const int64_t* dims, int dtype, con
     clear_error();
     if (!dims) return set_error(TVS_E_INVALID, "dims is NULL");
     if (ndim < 1 || ndim > 3) return set_error(TVS_E_SHAPE, "ndim must be 1, 2 or 3");
+    // One cached plan per problem and device, kept until the process ends.
+    // A plan's scratch and host-side state serve one run at a time: a call
+    // holds the entry while it enqueues, and its stream waits for the
+    // previous call's work before its own.
+    struct Entry {
+        tvs_plan* plan = nullptr;
+        std::mutex mu;
+        hipEvent_t done = nullptr;  // recorded after the last enqueued run
+        bool used = false;
+    };
     static std::mutex mu;
     static std::map<std::tuple<int, int64_t, int64_t, int64_t, int, int, int, int, int, int>,
-                    tvs_plan*>
+                    std::unique_ptr<Entry>>
         cache;
     int dev = 0;
     (void)hipGetDevice(&dev);
     auto key = std::make_tuple(ndim, dims[0], ndim > 1 ? dims[1] : 1, ndim > 2 ? dims[2] : 1,
                                dtype, shape, order, dependence, boundary, dev);
-    tvs_plan* p = nullptr;
+    Entry* e = nullptr;
     {
         std::lock_guard<std::mutex> lk(mu);
         auto it = cache.find(key);
         if (it != cache.end()) {
-            p = it->second;
+            e = it->second.get();
         } else {
+            tvs_plan* p = nullptr;
             int rc = stencil_plan(&p, ndim, dims, dtype, shape, order, dependence, boundary,
                                   nullptr);
             if (rc) return rc;
-            cache[key] = p;
+            std::unique_ptr<Entry> ne(new (std::nothrow) Entry());
+            if (!ne) {
+                stencil_plan_destroy(p);
+                return set_error(TVS_E_NOMEM, "out of host memory");
+            }
+            ne->plan = p;
+            e = ne.get();
+            cache.emplace(key, std::move(ne));
         }
     }
-    return stencil_run(p, grid, coeffs, T, stream);
+    std::lock_guard<std::mutex> hold(e->mu);
+    hipStream_t st = (hipStream_t)stream;
+    if (!e->done) TVS_HIP_TRY(hipEventCreateWithFlags(&e->done, hipEventDisableTiming));
+    if (e->used) TVS_HIP_TRY(hipStreamWaitEvent(st, e->done, 0));
+    int rc = stencil_run(e->plan, grid, coeffs, T, stream);
+    if (rc) return rc;
+    TVS_HIP_TRY(hipEventRecord(e->done, st));
+    e->used = true;
+    return TVS_OK;
 }
 
 int stencil_run_varcoef(tvs_plan* p, void* grid, const void* weights, int64_t T, void* stream) {

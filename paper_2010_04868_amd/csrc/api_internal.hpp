@@ -45,9 +45,14 @@ int enqueue_run(tvs_plan* p, void* grid, const double* coeffs, int64_t T, hipStr
 int enqueue_jacobi(tvs_plan* p, void* grid, const CoeffBuf& cb, int64_t T, hipStream_t st);
 int enqueue_gs(tvs_plan* p, void* grid, const CoeffBuf& cb, int64_t T, hipStream_t st);
 
-// Gauss-Seidel status: report an abort seen by an earlier run, then queue a
-// copy of the status word for the run just enqueued.
-int gs_check_status(tvs_plan* p, hipStream_t st);
+// Gauss-Seidel status.  gs_report_previous: TVS_E_DEVICE (and the word
+// cleared) if the copy queued after an earlier run has arrived and shows an
+// abort.  gs_queue_status_copy: queue a copy of the status word after the run
+// just enqueued on st.  gs_sync_status: wait for the plan's last copy, read
+// the word itself and report (and clear) an abort.
+int gs_report_previous(tvs_plan* p);
+int gs_queue_status_copy(tvs_plan* p, hipStream_t st);
+int gs_sync_status(tvs_plan* p);
 
 // Autotuning cache (TVS_TUNE_CACHE): schedule for a problem, if recorded.
 bool tune_cache_lookup(const Problem& p, Schedule* s);

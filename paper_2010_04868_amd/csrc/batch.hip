@@ -312,12 +312,6 @@ void set_lds_attributes() {
     set(batch_round_nd<T, 3, false, false, true>); set(batch_round_nd<T, 3, false, false, false>);
 }
 
-bool all_equal(const double* c, int n) {
-    for (int i = 1; i < n; ++i)
-        if (c[i] != c[0]) return false;
-    return true;
-}
-
 struct BatchPlan {
     std::vector<GroupLaunch> groups;
     std::vector<std::pair<tvs_plan*, int>> gs;  // Gauss-Seidel members (plan, index)
@@ -395,7 +389,7 @@ int prepare_batch(int n, tvs_plan* const* plans, void* const* grids, const doubl
             continue;
         }
         Variant v{p->prob.dtype, p->prob.ndim, p->prob.shape, p->prob.boundary,
-                  all_equal(coeffs[i], p->prob.order) ? 1 : 0};
+                  same_weight_bits(coeffs[i], p->prob.order) ? 1 : 0};
         groups[v].push_back(Member{p, grids[i], coeffs[i], T[i]});
     }
     set_lds_attributes<double>();
@@ -621,13 +615,31 @@ extern "C" int stencil_batch_run(int n, tvs_plan* const* plans, void* const* gri
         if (!plans[i] || !grids[i] || !coeffs[i]) return set_error(TVS_E_INVALID, "NULL member");
         if (T[i] < 0) return set_error(TVS_E_INVALID, "T < 0");
     }
+    // a plan or grid given twice would share scratch and data between members
+    // that run at the same time
+    {
+        std::vector<const void*> seen;
+        for (int i = 0; i < n; ++i)
+            if (T[i] > 0) {
+                seen.push_back(plans[i]);
+                seen.push_back(grids[i]);
+            }
+        std::sort(seen.begin(), seen.end());
+        if (std::adjacent_find(seen.begin(), seen.end()) != seen.end())
+            return set_error(TVS_E_INVALID, "a plan or grid appears twice in the batch");
+    }
+    for (int i = 0; i < n; ++i)
+        if (plans[i]->prob.dependence == TVS_GAUSS_SEIDEL && T[i] > 0) {
+            int rc = gs_report_previous(plans[i]);
+            if (rc) return rc;
+        }
     const char* env = std::getenv("TVS_BATCH_GRAPH");
     const bool use_graph = !(env && env[0] == '0');
     int rc = batch_run(n, plans, grids, coeffs, T, (hipStream_t)stream, use_graph, nullptr);
     if (rc) return rc;
     for (int i = 0; i < n; ++i)
         if (plans[i]->prob.dependence == TVS_GAUSS_SEIDEL && T[i] > 0) {
-            rc = gs_check_status(plans[i], (hipStream_t)stream);
+            rc = gs_queue_status_copy(plans[i], (hipStream_t)stream);
             if (rc) return rc;
         }
     return TVS_OK;

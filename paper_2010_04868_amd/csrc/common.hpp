@@ -56,7 +56,7 @@ struct Schedule {
     int c = 1;        // points per lane along the last axis
     int lanemap = 0;  // 0: levels fastest within a wave; 1: columns fastest
     int pl = 64;      // 1D: lanes per pipeline (16 = one DPP row, 64 = a wave)
-    int kern = 0;     // 2D: 0 = levels in lane groups with LDS planes, 1 = levels in registers
+    int kern = 0;     // kernel kind: 0 = levels in lane groups with LDS planes (the only one)
 };
 
 // Error reporting: thread-local message + code.

@@ -1,7 +1,8 @@
 // Band dispatch and geometry for the time-skewed Jacobi kernels.
+#include <cstring>
+
 #include "kernels.hpp"
 #include "tstp_nd.hpp"
-#include "tstp_reg2d.hpp"
 
 namespace tvs {
 
@@ -12,9 +13,9 @@ bool tstp_supported(const Problem& p) {
     return p.dependence == TVS_JACOBI && p.radius == 1 && p.ndim >= 1 && p.ndim <= 3;
 }
 
-static bool all_equal(const double* c, int n) {
+bool same_weight_bits(const double* c, int n) {
     for (int i = 1; i < n; ++i)
-        if (c[i] != c[0]) return false;
+        if (std::memcmp(&c[i], &c[0], sizeof(double)) != 0) return false;
     return true;
 }
 
@@ -38,23 +39,6 @@ bool band_geometry(const Problem& p, const Schedule& s, int k, BandGeom* g) {
         (p.ndim == 3 ? p.dims[1] * p.dims[2] : p.dims[1]) * (int64_t)p.elem_bytes();
     if (plane_bytes >= (int64_t(1) << 31)) return false;
     r.C = s.c;
-    if (p.ndim == 2 && s.kern == 1 && k == s.k && p.rule != TVS_RULE_LIFE) {
-        // register pipeline: a wave is a tile of 64*C columns, 4 tiles per workgroup
-        if (!reg2d_supported(p.dtype, k, r.C)) return false;
-        r.kern = 1;
-        r.W = 64 * r.C;
-        if (r.W <= 2 * k) return false;
-        r.Wv = r.W - 2 * k;
-        r.Lv = s.l > 0 ? s.l : 256;
-        r.ntx = ((int)p.dims[1] + r.Wv - 1) / r.Wv;
-        r.nseg = ((int)p.dims[0] + r.Lv - 1) / r.Lv;
-        r.G = 64;
-        r.NT = 256;
-        r.tiles_per_block = 4;
-        r.lds_bytes = 0;
-        *g = r;
-        return true;
-    }
     if (r.C != 4 && r.C != 8 && r.C != 16) return false;
     r.W = s.w;
     if (r.W <= 2 * k || r.W % r.C) return false;
@@ -87,28 +71,20 @@ bool band_geometry(const Problem& p, const Schedule& s, int k, BandGeom* g) {
 hipError_t launch_tstp_band(const Problem& p, const BandGeom& g, const void* in, void* out,
                             const void* coeffs, hipStream_t st) {
     if (p.ndim == 1) return launch_tstp1d(p, g, in, out, coeffs, st);
-    if (g.kern == 1) {
-        double cd[kMaxPoints];
-        if (p.dtype == TVS_F64)
-            for (int q = 0; q < p.order; ++q) cd[q] = ((const Coeffs<double>*)coeffs)->c[q];
-        else
-            for (int q = 0; q < p.order; ++q) cd[q] = ((const Coeffs<float>*)coeffs)->c[q];
-        return launch_reg2d(p, g, in, out, coeffs, all_equal(cd, p.order), st);
-    }
     if (p.rule == TVS_RULE_LIFE)
         return launch_nd_life_2d(p, g, (const uint32_t*)in, (uint32_t*)out, st);
     if (p.dtype == TVS_F64) {
         auto& cf = *(const Coeffs<double>*)coeffs;
         double cd[kMaxPoints];
         for (int q = 0; q < p.order; ++q) cd[q] = cf.c[q];
-        const bool uni = all_equal(cd, p.order);
+        const bool uni = same_weight_bits(cd, p.order);
         return p.ndim == 2 ? launch_nd_f64_2d(p, g, (const double*)in, (double*)out, cf, uni, st)
                            : launch_nd_f64_3d(p, g, (const double*)in, (double*)out, cf, uni, st);
     }
     auto& cf = *(const Coeffs<float>*)coeffs;
     double cd[kMaxPoints];
     for (int q = 0; q < p.order; ++q) cd[q] = cf.c[q];
-    const bool uni = all_equal(cd, p.order);
+    const bool uni = same_weight_bits(cd, p.order);
     return p.ndim == 2 ? launch_nd_f32_2d(p, g, (const float*)in, (float*)out, cf, uni, st)
                        : launch_nd_f32_3d(p, g, (const float*)in, (float*)out, cf, uni, st);
 }

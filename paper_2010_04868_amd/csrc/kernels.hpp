@@ -25,9 +25,9 @@ struct BandGeom {
     int ntx = 1, nty = 1, nseg = 1;  // tile counts
     int pl = 64;         // 1D: lanes per pipeline
     int lanemap = 0;
-    int kern = 0;        // 0 = LDS level planes, 1 = register pipeline (2D)
+    int kern = 0;        // 0 = LDS level planes (the only kind)
     size_t lds_bytes = 0;
-    int tiles_per_block = 1;  // register pipeline: one tile per wave, four waves
+    int tiles_per_block = 1;
     int64_t tiles() const { return (int64_t)ntx * nty * nseg; }
     int64_t blocks() const { return (tiles() + tiles_per_block - 1) / tiles_per_block; }
 };
@@ -53,6 +53,13 @@ hipError_t launch_gs(const Problem& p, void* grid, const void* coeffs, int sweep
 hipError_t gs_layout_out(const Problem& p, void* grid, void* work, hipStream_t st);
 // Status word written by the Gauss-Seidel kernel (0 = ok) lives in `work`.
 hipError_t gs_read_status(const void* work, int* status, hipStream_t st);
+
+// True when every weight has the bit pattern of the first.  Only then may an
+// interior tile form each value's product once and reuse it for every
+// offset: weights that compare equal but differ in sign (-0.0 and +0.0)
+// give products of different sign, and the canonical sum of those can be
+// +0.0 where the shared product would give -0.0.
+bool same_weight_bits(const double* c, int n);
 
 // Whether the schedule's kernel exists for this problem.
 bool tstp_supported(const Problem& p);

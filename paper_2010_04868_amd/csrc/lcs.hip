@@ -224,9 +224,11 @@ extern "C" {
 int stencil_lcs_plan(tvs_lcs** out, int64_t m, int64_t n, const char* tuning) {
     clear_error();
     if (!out) return set_error(TVS_E_INVALID, "out is NULL");
-    constexpr int64_t kMax = ((int64_t)1 << 31) - 256;
+    // the kernels index rows and columns in 32 bits, up to a tile (at most
+    // 1024 rows, 4096 columns) plus a pipeline's lag past the last one
+    constexpr int64_t kMax = (int64_t)1 << 30;
     if (m < 0 || n < 0 || m > kMax || n > kMax)
-        return set_error(TVS_E_SHAPE, "sequence lengths must lie in 0..2^31-256");
+        return set_error(TVS_E_SHAPE, "sequence lengths must lie in 0..2^30");
     // measured on 200000 x 200000 over widths 128..2048 and heights 64..1024:
     // 1024 x 256 best (1012 GCells/s; 512 x 256: 906, 1024 x 512: 921)
     int tw = 1024, rows = 256;

@@ -160,10 +160,9 @@ std::string format_tuning(const Problem& p, const Schedule& s) {
 
 // Workgroups that fit on one CU for a band geometry (LDS and wave limits).
 int wgs_per_cu(const BandGeom& g) {
-    // the LDS pipelines use about 100-128 VGPRs (four waves per SIMD), the
-    // register pipeline about 250 (two waves per SIMD)
+    // the LDS pipelines use about 100-128 VGPRs (four waves per SIMD)
     int waves = std::max(1, (g.NT + 63) / 64);
-    int by_waves = std::max(1, (g.kern == 1 ? 8 : 16) / waves);
+    int by_waves = std::max(1, 16 / waves);
     int by_lds = g.lds_bytes ? (int)((160 * 1024) / g.lds_bytes) : by_waves;
     return std::max(1, std::min(by_waves, by_lds));
 }
@@ -175,7 +174,7 @@ double band_cost(const Problem& p, const BandGeom& g) {
     const double slots = (double)cus * wgs_per_cu(g);
     const double tiles = (double)g.blocks();
     const double rounds = std::ceil(tiles / slots);
-    const double steps = g.Lv + (g.kern == 1 ? 2.0 : 3.0) * g.k;
+    const double steps = g.Lv + 3.0 * g.k;
     return rounds * steps;
 }
 
@@ -285,8 +284,8 @@ Schedule default_schedule(const Problem& p) {
 int check_schedule(const Problem& p, const Schedule& s) {
     if (s.method == TVS_METHOD_PLAIN) return TVS_OK;
     if (s.k < 1) return set_error(TVS_E_INVALID, "k must be >= 1");
-    if (p.rule == TVS_RULE_LIFE && s.kern != 0)
-        return set_error(TVS_E_INVALID, "Game of Life runs on the LDS pipeline only (kern=0)");
+    if (s.kern != 0)
+        return set_error(TVS_E_INVALID, "kern must be 0 (the LDS level-plane pipeline)");
     if (p.dependence == TVS_GAUSS_SEIDEL) {
         const int kmax = p.ndim == 2 ? 256 : 1024;
         if (s.k > kmax)

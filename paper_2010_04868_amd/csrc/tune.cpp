@@ -1,4 +1,4 @@
-// Autotuner: search time-tile depth, tile shape, lane map and kernel kind
+// Autotuner: search time-tile depth, tile shape and lane map
 // for one problem on the device, keep the fastest, and remember it.
 //
 // The paper searched power-of-two block sizes by hand and notes that the
@@ -24,8 +24,6 @@
 #include "plan.hpp"
 
 namespace tvs {
-
-bool reg2d_supported(int dtype, int k, int c);
 
 std::string problem_key(const Problem& p) {
     std::ostringstream o;
@@ -125,17 +123,6 @@ std::vector<Schedule> tune_candidates(const Problem& p) {
                         s.l = 0;
                         add(s);
                     }
-        for (int k : {4, 6, 8, 16})
-            for (int c : {2, 4, 8})
-                if (reg2d_supported(p.dtype, k, c)) {
-                    Schedule s = base;
-                    s.kern = 1;
-                    s.k = k;
-                    s.c = c;
-                    s.w = 64 * c;
-                    s.l = 0;
-                    add(s);
-                }
     } else {
         const int shapes[][2] = {{32, 16}, {64, 16}, {64, 32}, {32, 32}, {128, 8}, {128, 16}};
         for (int c : {4, 8})
@@ -166,7 +153,7 @@ std::vector<Schedule> tune_candidates(const Problem& p) {
 
 namespace {
 
-__global__ void count_diff(const unsigned long long* a, const unsigned long long* b, int64_t n,
+__global__ void count_diff(const unsigned* a, const unsigned* b, int64_t n,
                            unsigned long long* out) {
     unsigned long long local = 0;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
@@ -219,7 +206,7 @@ extern "C" int stencil_tune(tvs_plan* p, void* grid, const double* coeffs, int64
     (void)hipStreamSynchronize(st);
     double best_ms = 1e300;
     Schedule best_s = original;
-    const int64_t words = (int64_t)(bytes / 8);
+    const int64_t words = (int64_t)(bytes / 4);  // every grid is whole 4-byte elements
     for (size_t i = 0; i < cands.size() && rc == TVS_OK; ++i) {
         p->sched = cands[i];
         // restore, run once (also warms up), compare with the first candidate
@@ -231,7 +218,7 @@ extern "C" int stencil_tune(tvs_plan* p, void* grid, const double* coeffs, int64
         } else {
             hipLaunchKernelGGL(zero_u64, dim3(1), dim3(1), 0, st, dcount);
             hipLaunchKernelGGL(count_diff, dim3(1024), dim3(256), 0, st,
-                               (const unsigned long long*)grid, (const unsigned long long*)ref,
+                               (const unsigned*)grid, (const unsigned*)ref,
                                words, dcount);
             unsigned long long diff = 0;
             (void)hipMemcpyAsync(&diff, dcount, sizeof diff, hipMemcpyDeviceToHost, st);
@@ -260,6 +247,9 @@ extern "C" int stencil_tune(tvs_plan* p, void* grid, const double* coeffs, int64
             (void)hipEventElapsedTime(&ms, e0, e1);
             ms_best = std::min(ms_best, (double)ms * (double)T_probe / (double)T_time);
         }
+        // a Gauss-Seidel candidate whose bounded waits expired produced no result
+        if (rc == TVS_OK && pr.dependence == TVS_GAUSS_SEIDEL) rc = gs_sync_status(p);
+        if (rc) break;
         if (std::getenv("TVS_LOG"))
             std::fprintf(stderr, "[tvs tune] %s: %.4f ms\n", format_tuning(pr, cands[i]).c_str(),
                          ms_best);

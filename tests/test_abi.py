@@ -78,8 +78,11 @@ def test_plan_info_reports_schedule():
     assert inf["k"] >= 1 and inf["s"] == 2 and inf["tile_w"] > 2 * inf["k"]
     q = tvs.Plan((100, 100), F32, STAR, 5, tuning="method=plain")
     assert q.info()["method"] == 0 and q.info()["k"] == 1
-    r = tvs.Plan((64, 64), F64, STAR, 5, tuning="method=tstp,kern=1,k=8,c=4")
-    assert r.info()["k"] == 8 and r.info()["lane_c"] == 4 and r.info()["kern"] == 1
+    r = tvs.Plan((64, 64), F64, STAR, 5, tuning="method=tstp,k=8,w=128,c=4")
+    assert r.info()["k"] == 8 and r.info()["lane_c"] == 4 and r.info()["kern"] == 0
+    # only the LDS level-plane kernel exists
+    assert code_of(lambda: tvs.Plan((64, 64), F64, STAR, 5, tuning="method=tstp,kern=1,k=8,c=4")) \
+        == E["TVS_E_INVALID"]
 
 
 @pytest.mark.parametrize("dims,shape,order,dep", [
@@ -153,7 +156,7 @@ def test_life_plans_without_device():
     assert q.info()["method"] == 0 and q.info()["boundary"] == PERIODIC
     r = tvs.LifePlan((64, 80), DIRICHLET, inf["tuning"])
     assert r.info()["tuning"] == inf["tuning"]
-    # 2D only; the register pipeline and weighted int32 grids do not exist
+    # 2D only; kern=1 and weighted int32 grids do not exist
     assert code_of(lambda: tvs.LifePlan((8, 8, 8))) == E["TVS_E_SHAPE"]
     assert code_of(lambda: tvs.LifePlan((2, 8))) == E["TVS_E_SHAPE"]
     assert code_of(lambda: tvs.LifePlan((8, 8), 3)) == E["TVS_E_INVALID"]
@@ -184,6 +187,12 @@ def test_lcs_plans_without_device():
         assert code_of(lambda: tvs.LcsPlan(10, 10, bad)) == E["TVS_E_INVALID"]
     assert code_of(lambda: tvs.LcsPlan(-1, 10)) == E["TVS_E_SHAPE"]
     assert code_of(lambda: tvs.LcsPlan(10, 1 << 31)) == E["TVS_E_SHAPE"]
+    # rows and columns are indexed in 32 bits: lengths up to 2^30, so the last
+    # tile plus its pipeline lag stays below 2^31 for every tiling
+    assert tvs.LcsPlan(1 << 30, 1 << 30, "w=4096,r=512").tile_width == 4096
+    assert code_of(lambda: tvs.LcsPlan((1 << 30) + 1, 10, "r=1024")) == E["TVS_E_SHAPE"]
+    assert code_of(lambda: tvs.LcsPlan(10, (1 << 30) + 1)) == E["TVS_E_SHAPE"]
+    assert code_of(lambda: tvs.LcsPlan((1 << 31) - 256, 10)) == E["TVS_E_SHAPE"]
     fake = ctypes.c_void_p(0x1000)
     assert lib.stencil_lcs_run(p.handle if hasattr(p, "handle") else p._h, None, fake, fake,
                                fake, None) == E["TVS_E_INVALID"]
@@ -204,6 +213,33 @@ def test_run_argument_errors_without_device():
     assert lib.stencil_batch_run(0, None, None, None, None, None) == 0
     assert lib.stencil_batch_run(-1, None, None, None, None, None) == E["TVS_E_INVALID"]
     assert lib.stencil_plan_destroy(None) == 0
+    # a plan that never ran has no abort to report
+    assert lib.stencil_plan_check(p.handle) == 0
+    assert lib.stencil_plan_check(None) == E["TVS_E_INVALID"]
+    g = tvs.Plan((16, 16), F64, STAR, 5, GAUSS_SEIDEL)
+    assert lib.stencil_plan_check(g.handle) == 0
+
+
+def test_batch_rejects_repeated_plans_and_grids():
+    """Members run at the same time: one plan (its scratch) or one grid given
+    twice would be shared by two of them.  Rejected before any device work."""
+    lib = _lib.load()
+    a = tvs.Plan((16, 16), F64, STAR, 5)
+    b = tvs.Plan((16, 16), F64, STAR, 5)
+    gs = tvs.Plan((16, 16), F64, STAR, 5, GAUSS_SEIDEL)
+    w = (ctypes.c_double * 5)(*([0.2] * 5))
+    C = (ctypes.POINTER(ctypes.c_double) * 2)(w, w)
+
+    def batch(p0, p1, g0, g1, t0=3, t1=3):
+        P = (ctypes.c_void_p * 2)(p0.handle.value, p1.handle.value)
+        G = (ctypes.c_void_p * 2)(g0, g1)
+        Tn = (ctypes.c_int64 * 2)(t0, t1)
+        return lib.stencil_batch_run(2, P, G, C, Tn, None)
+    assert batch(a, a, 0x1000, 0x2000) == E["TVS_E_INVALID"]
+    assert batch(gs, gs, 0x1000, 0x2000) == E["TVS_E_INVALID"]
+    assert batch(a, b, 0x1000, 0x1000) == E["TVS_E_INVALID"]
+    assert batch(a, gs, 0x3000, 0x3000) == E["TVS_E_INVALID"]
+    assert "twice" in lib.stencil_last_error().decode()
 
 
 def test_tuning_cache_roundtrip(tmp_path, monkeypatch):

@@ -22,14 +22,26 @@ from paper_2010_04868_amd.inputs import DIRICHLET, F32, F64, I32, PERIODIC
 pytestmark = pytest.mark.gpu
 
 
-def run_gpu(p, u0):
+def run_gpu(p, u0, tuning=None):
     import torch
 
     import paper_2010_04868_amd as tvs
     g = torch.from_numpy(u0).to("cuda")
-    tvs.Plan.for_problem(p).run(g, p.coeffs, p.T)
+    tvs.Plan.for_problem(p, tuning).run(g, p.coeffs, p.T)
     torch.cuda.synchronize()
     return g.cpu().numpy()
+
+
+def report(name, value):
+    """Measured figures (FP32 errors) go to stdout and, on a GPU machine, to a
+    file next to the run's other outputs."""
+    import os
+    line = f"{name}: {value:.3e}"
+    print(line, flush=True)
+    out = os.path.join(os.environ.get("GRAFT_REPO_ROOT", "."), "gpurun_out")
+    if os.path.isdir(out):
+        with open(os.path.join(out, "fp32_errors.txt"), "a") as f:
+            f.write(line + "\n")
 
 
 def window_check(p, u0, got, lo, size, prec_arr=None):
@@ -70,29 +82,58 @@ def parallel_windows(p, u0, got, los, size):
         return {lo: f.result() for lo, f in futs.items()}
 
 
+# The benchmark's schedule for the 8192^2 box (the autotuner's pick on the
+# device) and the library's default differ only in the lane map: tiles of
+# 256 columns (240 valid) and segments of 288 rows.
+BOX_SCHEDULES = (None, "method=tstp,k=8,w=256,h=1,l=288,c=8,lanemap=0")
+
+
 def test_box2d9p_full_size_windows():
     p = inputs.box2d9p()                 # 8192^2, FP64, T = 1000
     u0 = inputs.make_grid(p)
-    got = run_gpu(p, u0)
     n = p.dims[0]
-    los = ((0, 0), (0, n - 32), (n - 32, n - 32), (n // 2 - 8, n // 3))
-    for lo, (g, r) in parallel_windows(p, u0, got, los, 32).items():
-        assert_bitwise(g, r, f"window at {lo}")
+    # corners, an interior point, and (4016, 2624): a 32 x 32 window across
+    # the corner where four interior tiles meet (row 4032 = 14 x 288,
+    # column 2640 = 11 x 240), so seams between equal-weight tiles are compared
+    los = ((0, 0), (0, n - 32), (n - 32, n - 32), (n // 2 - 8, n // 3), (4016, 2624))
+    refs = None
+    for tuning in BOX_SCHEDULES:
+        got = run_gpu(p, u0, tuning)
+        if refs is None:
+            refs = {lo: r for lo, (_, r) in parallel_windows(p, u0, got, los, 32).items()}
+        for lo in los:
+            g = got[lo[0]:lo[0] + 32, lo[1]:lo[1] + 32]
+            assert_bitwise(g, refs[lo], f"window at {lo}, schedule {tuning}")
 
 
-def test_box2d9p_fp32_error_and_mirror():
-    p = inputs.box2d9p(dtype=F32, T=100)
+@pytest.mark.parametrize("T", [100, 1000])
+def test_box2d9p_fp32_error_and_mirror(T):
+    """FP32 storage and arithmetic: bit-exact to the FP32 mirror, and within
+    1e-5 relative error of the FP64 oracle on the same float32-drawn values at
+    T = 100 (measured and reported at T = 100 and T = 1000; no bound is
+    claimed at T = 1000)."""
+    p = inputs.box2d9p(dtype=F32, T=T)
     u0 = inputs.make_grid(p)
     got = run_gpu(p, u0)
-    for lo in ((0, 0), (4000, 5000)):
-        g, r32 = window_check(p, u0, got, lo, 64)
+    los = ((0, 0), (4000, 5000), (4016, 2624))
+    # the FP32 mirror and the FP64 oracle (on the same float32-drawn values)
+    # for every window, side by side
+    p64 = p.with_(dtype=F64)
+    u64, g64 = u0.astype(np.float64), got.astype(np.float64)
+    with cf.ThreadPoolExecutor(max_workers=2 * len(los)) as ex:
+        f32 = {lo: ex.submit(window_check, p, u0, got, lo, 64) for lo in los}
+        f64 = {lo: ex.submit(window_check, p64, u64, g64, lo, 64) for lo in los}
+    worst = 0.0
+    for lo in los:
+        g, r32 = f32[lo].result()
         assert_bitwise(g, r32, f"fp32 mirror window at {lo}")
-        # FP64 oracle on the same (float32-drawn) values
-        p64 = p.with_(dtype=F64)
-        _, r64 = window_check(p64, u0.astype(np.float64), got.astype(np.float64), lo, 64)
+        _, r64 = f64[lo].result()
         inner = (slice(1, None), slice(1, None)) if lo == (0, 0) else (slice(None), slice(None))
-        err = max_rel_err(g[inner], r64[inner])
-        assert err <= 1e-5, err
+        worst = max(worst, max_rel_err(g[inner], r64[inner]))
+    report(f"2D 9-point box FP32 8192^2 T={T}: max relative error vs the FP64 oracle "
+           "(three 64 x 64 windows)", worst)
+    if T == 100:
+        assert worst <= 1e-5, worst
 
 
 def test_star3d7p_full_size_windows():
@@ -103,6 +144,16 @@ def test_star3d7p_full_size_windows():
         los = ((0, 0, 0), (300, 17, 511 - 12))
         for lo, (g, r) in parallel_windows(p, u0, got, los, 12).items():
             assert_bitwise(g, r, f"3D {p.name} window at {lo}")
+        if dt == F32:
+            # the FP64 oracle on the same float32-drawn values
+            p64 = p.with_(dtype=F64)
+            u64, g64 = u0.astype(np.float64), got.astype(np.float64)
+            worst = 0.0
+            for lo, (g, r) in parallel_windows(p64, u64, g64, los, 12).items():
+                worst = max(worst, max_rel_err(g, r))
+            report("3D 7-point star FP32 512^3 periodic T=100: max relative error vs the FP64 "
+                   "oracle (two 12^3 windows)", worst)
+            assert worst <= 1e-5, worst
 
 
 def test_life2d_full_size_windows():

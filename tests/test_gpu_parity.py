@@ -27,8 +27,7 @@ TUNINGS = {
         "method=tstp,k=5,l=20,pl=16", "method=tstp,k=64,l=3,pl=64"],
     2: [None, "method=plain", "method=tstp,k=4,w=64,c=8,l=40,lanemap=0",
         "method=tstp,k=4,w=64,c=8,l=40,lanemap=1", "method=tstp,k=3,w=48,c=4,l=17,lanemap=0",
-        "method=tstp,k=8,w=128,c=16,l=64,lanemap=1", "method=tstp,k=16,w=256,c=8,l=50",
-        "method=tstp,kern=1,k=8,c=4,l=37", "method=tstp,kern=1,k=16,c=2,l=20"],
+        "method=tstp,k=8,w=128,c=16,l=64,lanemap=1", "method=tstp,k=16,w=256,c=8,l=50"],
     3: [None, "method=plain", "method=tstp,k=2,w=16,h=8,c=4,l=10",
         "method=tstp,k=3,w=16,h=12,c=8,l=7,lanemap=0", "method=tstp,k=4,w=32,h=16,c=16,l=5",
         "method=tstp,k=2,w=64,h=32,c=8,l=9,lanemap=1"],
