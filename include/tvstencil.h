@@ -281,6 +281,24 @@ int stencil_lcs_tile_rows(const tvs_lcs *plan);
  */
 int stencil_lcs_run(tvs_lcs *plan, const uint8_t *a, const uint8_t *b, int32_t *row,
                     int32_t *col, void *stream);
+/*
+ * stencil_lcs_run for callers that cannot allocate device memory (code under
+ * hipGraph capture, serving loops, harnesses that forbid hipMalloc): the same
+ * launches and results, with the per-tile-column corner array in a static
+ * device array of 65536 int32 (256 KiB; every device the library runs on
+ * holds one until the process ends) instead of memory the plan allocates.
+ * The call allocates nothing and frees nothing.  Arguments as for
+ * stencil_lcs_run.
+ *   - the plan may have at most 65536 tile columns, ceil(n / w) <= 65536
+ *     (n <= 67108864 with the default w = 1024); larger: TVS_E_SHAPE;
+ *   - all calls on one device share that device's array and nothing in it
+ *     needs to start at zero (each run writes every entry it reads first);
+ *     calls that overlap on one device (on several streams, or from several
+ *     threads without ordering) race on it and give invalid results.
+ */
+int stencil_lcs_run_noalloc(const tvs_lcs *plan, const uint8_t *a, const uint8_t *b,
+                            int32_t *row, int32_t *col, void *stream);
+
 /* Free the plan (waits for the device first).  NULL is a no-op. */
 int stencil_lcs_destroy(tvs_lcs *plan);
 

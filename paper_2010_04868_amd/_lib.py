@@ -86,6 +86,7 @@ SIGNATURES = [
     ("stencil_lcs_tile_width", ctypes.c_int, [vp]),
     ("stencil_lcs_tile_rows", ctypes.c_int, [vp]),
     ("stencil_lcs_run", ctypes.c_int, [vp, vp, vp, vp, vp, vp]),
+    ("stencil_lcs_run_noalloc", ctypes.c_int, [vp, vp, vp, vp, vp, vp]),
     ("stencil_lcs_destroy", ctypes.c_int, [vp]),
     ("stencil_last_error", ctypes.c_char_p, []),
     ("stencil_version", ctypes.c_char_p, []),

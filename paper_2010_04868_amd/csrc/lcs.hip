@@ -34,6 +34,7 @@
 #include <climits>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <type_traits>
@@ -47,6 +48,13 @@ struct tvs_lcs {
     int nI = 0, nJ = 0;
     int32_t* corner = nullptr;
 };
+
+// Corner array of the allocation-free run (stencil_lcs_run_noalloc): one
+// int32 per tile column, held by every device the library runs on until the
+// process ends.  Host code never uses this name as an address; it takes the
+// device's own address from hipGetSymbolAddress (noalloc_corner below).
+constexpr int kLcsNoAllocCorners = 65536;
+static __device__ __align__(256) int32_t scratch[kLcsNoAllocCorners];
 
 namespace tvs {
 namespace {
@@ -187,6 +195,27 @@ __global__ __launch_bounds__(1024) void lcs_diag(const uint8_t* __restrict__ a,
     if (w == W - 1 && lane == 63 && I + 1 < nI) corner[J] = west0;  // lcs[x0+64W-1][y0-1]
 }
 
+// The device address of `scratch` on the current device, looked up once per
+// device with that device current (each device holds its own copy).
+int noalloc_corner(int32_t** out) {
+    constexpr int kMaxDevices = 64;
+    static std::mutex mu;
+    static int32_t* addr[kMaxDevices] = {};
+    int dev = 0;
+    TVS_HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices)
+        return set_error(TVS_E_DEVICE, "device index beyond the scratch table");
+    std::lock_guard<std::mutex> lk(mu);
+    if (!addr[dev]) {
+        void* ptr = nullptr;
+        TVS_HIP_TRY(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        if (!ptr) return set_error(TVS_E_DEVICE, "no device address for the LCS scratch array");
+        addr[dev] = (int32_t*)ptr;
+    }
+    *out = addr[dev];
+    return TVS_OK;
+}
+
 }  // namespace
 
 static size_t lcs_lds_bytes(int tw, int rows) {
@@ -252,22 +281,17 @@ int stencil_lcs_plan(tvs_lcs** out, int64_t m, int64_t n, const char* tuning) {
 int stencil_lcs_tile_width(const tvs_lcs* p) { return p ? p->tw : TVS_E_INVALID; }
 int stencil_lcs_tile_rows(const tvs_lcs* p) { return p ? p->rows : TVS_E_INVALID; }
 
-int stencil_lcs_run(tvs_lcs* p, const uint8_t* a, const uint8_t* b, int32_t* row, int32_t* col,
-                    void* stream) {
-    clear_error();
-    if (!p || !row || !col || (p->m > 0 && !a) || (p->n > 0 && !b))
-        return set_error(TVS_E_INVALID, "NULL argument");
-    hipStream_t st = (hipStream_t)stream;
-    if (!p->corner) {
-        void* ptr = nullptr;
-        if (hipMalloc(&ptr, (size_t)std::max(1, p->nJ) * sizeof(int32_t)) != hipSuccess)
-            return set_error(TVS_E_NOMEM, "hipMalloc of the LCS corner array failed");
-        p->corner = (int32_t*)ptr;
-    }
+}  // extern "C"
+
+namespace tvs {
+
+// The run's launches, with the corner array of at least max(1, nJ) int32.
+static int lcs_enqueue(const tvs_lcs* p, const uint8_t* a, const uint8_t* b, int32_t* row,
+                       int32_t* col, int32_t* corner, hipStream_t st) {
     const int m = (int)p->m, n = (int)p->n;
     const int nthreads = std::max(1, p->nJ);
     hipLaunchKernelGGL(lcs_init, dim3((unsigned)((nthreads + 255) / 256)), dim3(256), 0, st, row,
-                       col, p->corner, m, n, p->tw, p->nJ);
+                       col, corner, m, n, p->tw, p->nJ);
     TVS_HIP_TRY(hipGetLastError());
     if (m == 0 || n == 0) return TVS_OK;
     const size_t lds = lcs_lds_bytes(p->tw, p->rows);
@@ -280,10 +304,42 @@ int stencil_lcs_run(tvs_lcs* p, const uint8_t* a, const uint8_t* b, int32_t* row
     for (int d = 0; d < p->nI + p->nJ - 1; ++d) {
         const int ilo = std::max(0, d - (p->nJ - 1)), ihi = std::min(p->nI - 1, d);
         hipLaunchKernelGGL(lcs_diag, dim3((unsigned)(ihi - ilo + 1)), dim3(p->rows), lds, st, a, b, row,
-                           col, p->corner, m, n, p->tw, p->nI, p->nJ, d);
+                           col, corner, m, n, p->tw, p->nI, p->nJ, d);
     }
     TVS_HIP_TRY(hipGetLastError());
     return TVS_OK;
+}
+
+}  // namespace tvs
+
+extern "C" {
+
+int stencil_lcs_run(tvs_lcs* p, const uint8_t* a, const uint8_t* b, int32_t* row, int32_t* col,
+                    void* stream) {
+    clear_error();
+    if (!p || !row || !col || (p->m > 0 && !a) || (p->n > 0 && !b))
+        return set_error(TVS_E_INVALID, "NULL argument");
+    if (!p->corner) {
+        void* ptr = nullptr;
+        if (hipMalloc(&ptr, (size_t)std::max(1, p->nJ) * sizeof(int32_t)) != hipSuccess)
+            return set_error(TVS_E_NOMEM, "hipMalloc of the LCS corner array failed");
+        p->corner = (int32_t*)ptr;
+    }
+    return lcs_enqueue(p, a, b, row, col, p->corner, (hipStream_t)stream);
+}
+
+int stencil_lcs_run_noalloc(const tvs_lcs* p, const uint8_t* a, const uint8_t* b, int32_t* row,
+                            int32_t* col, void* stream) {
+    clear_error();
+    if (!p || !row || !col || (p->m > 0 && !a) || (p->n > 0 && !b))
+        return set_error(TVS_E_INVALID, "NULL argument");
+    if (p->nJ > kLcsNoAllocCorners)
+        return set_error(TVS_E_SHAPE, "stencil_lcs_run_noalloc: ceil(n / w) tile columns exceed "
+                                      "the 65536 entries of the static corner array");
+    int32_t* corner = nullptr;
+    int rc = noalloc_corner(&corner);
+    if (rc) return rc;
+    return lcs_enqueue(p, a, b, row, col, corner, (hipStream_t)stream);
 }
 
 int stencil_lcs_destroy(tvs_lcs* p) {
