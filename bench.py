@@ -154,6 +154,9 @@ WORKLOADS = {
     "life2d": (lambda inp, n, T: inp.life2d(**_kw(n, T)), "Game of Life B2S23, int32 cells"),
     "gs3d7p": (lambda inp, n, T: inp.gs3d7p(**_kw(n, T)), "3D 7-point Gauss-Seidel FP64"),
     "star1d5p": (lambda inp, n, T: inp.star1d5p(**_kw(n, T)), "1D 5-point (radius 2) Jacobi FP64"),
+    "star2d9p": (lambda inp, n, T: inp.star2d9p(**_kw(n, T)),
+                 "2D 9-point star (radius 2) Jacobi FP64"),
+    "vc2d5p": (None, "2D 5-point Jacobi with variable coefficients FP64"),
     "lcs": (None, "longest common subsequence, 200000 x 200000"),
     "vc1d3p": (None, "1D 3-point Jacobi with variable coefficients FP64"),
 }
@@ -185,6 +188,8 @@ def describe(p, inputs) -> str:
         return f"2D Game of Life B2S23 {dims} int32 cells, T={p.T}, {bnd}, cells live w.p. 1/2"
     kind = {(inputs.STAR, 3): "3-point", (inputs.STAR, 5): "5-point", (inputs.STAR, 7): "7-point",
             (inputs.BOX, 9): "9-point box"}.get((p.shape, p.order), f"{p.order}-point")
+    if p.radius > 1:
+        kind += f" {'box' if p.shape == inputs.BOX else 'star'} (radius {p.radius})"
     dep = "Gauss-Seidel (in place, lexicographic)" if p.dependence == inputs.GAUSS_SEIDEL else \
         "Jacobi"
     dims = "x".join(str(d) for d in p.dims)
@@ -193,6 +198,8 @@ def describe(p, inputs) -> str:
         ("zero Dirichlet border" if p.zero_border else "fixed Dirichlet ends")
     w = sorted(set(p.coeffs))
     wt = "weights " + ("1/9" if w == [1.0 / 9.0] else "/".join(f"{x:g}" for x in p.coeffs))
+    if p.radius > 1 and p.zero_border:
+        bnd = f"zero Dirichlet border {p.radius} points deep"
     return f"{p.ndim}D {kind} {dep} {dims} {dt}, T={p.T}, {bnd}, {wt}"
 
 
@@ -217,7 +224,7 @@ def kernel_name(p, info, inputs) -> str:
         return {1: "gs1d sweep pipeline", 2: "gs2d wavefront", 3: "gs3d_planes"}[p.ndim]
     if p.ndim == 1:
         return "tstp1d_r" if info.get("radius", 1) > 1 else "tstp1d"
-    return "tstp_nd"
+    return "tstp_ndr" if info.get("radius", 1) > 1 else "tstp_nd"
 
 
 def cpu_model() -> str:
@@ -254,21 +261,26 @@ def cpu_baseline(p, budget_s=15.0):
                       f"{dt:.1f} s"}
 
 
-def serving_run(torch, tvs, inputs, n_req, rho, seed=5):
-    """A Poisson stream through the server at offered load rho of its capacity,
-    next to the same requests run one at a time (tuned schedules, then the plain
-    one-step-per-launch sweep).  Every form starts from the host input and ends
-    with the result on the host, as a served request does."""
+def serving_run(torch, tvs, inputs, n_req, rhos, seed=5, budget=4 << 30):
+    """A Poisson stream through the server at offered loads rho of its
+    capacity, next to the same requests run one at a time (tuned schedules,
+    then the plain one-step-per-launch sweep).  The requests follow the
+    serving mix's full distribution (2D sides 64..4096, 3D 32..256, 1D
+    1e3..1e6, T 10..1000); n_req of them.  Every form starts from the host
+    input and ends with the result on the host, as a served request does."""
     import numpy as np
-    side2d, side3d, n1d, steps = (64, 2048), (32, 160), (1000, 1000000), (10, 200)
+    side2d, side3d, n1d, steps = (64, 4096), (32, 256), (1000, 1000000), (10, 1000)
     mix = inputs.serving_mix(n_req, seed=seed, side2d=side2d, side3d=side3d, n1d=n1d,
                              steps=steps)
+    t_gen = time.perf_counter()
     grids = [inputs.make_grid(r.problem) for r in mix]
+    log(f"serving: {len(mix)} request grids generated ({sum(g.nbytes for g in grids) / 2**30:.2f} "
+        f"GiB, {time.perf_counter() - t_gen:.1f} s)")
     outs = [np.empty_like(g) for g in grids]
     total_updates = sum(r.problem.updated_points() * r.problem.T for r in mix)
 
     def serve(arrivals):
-        srv = tvs.Server(hbm_budget=8 << 30, max_slots=64, chunk_steps=64)
+        srv = tvs.Server(hbm_budget=budget, max_slots=64, chunk_steps=64)
         try:
             t_base = time.perf_counter()
             ids = []
@@ -293,35 +305,47 @@ def serving_run(torch, tvs, inputs, n_req, rho, seed=5):
 
     serve([0.0] * min(8, len(mix)))  # warm-up: kernels loaded, arena touched
     # capacity: everything submitted at once
+    t0 = time.perf_counter()
     stamps, st_cap = serve([0.0] * len(mix))
     makespan = max(s[3] for s in stamps) - min(s[0] for s in stamps)
     capacity_rps = len(mix) / makespan
-    # Poisson arrivals at rho * capacity
-    rng = np.random.default_rng(seed)
-    gaps = rng.exponential(1.0 / (rho * capacity_rps), size=len(mix))
-    arrivals = np.cumsum(gaps) - gaps[0]
-    stamps, st = serve(list(arrivals))
-    lat = np.array([s[3] - s[0] for s in stamps])
-    span = max(s[3] for s in stamps) - min(s[0] for s in stamps)
+    capacity = total_updates / makespan / 1e9
+    log(f"serving: capacity {capacity:.1f} GStencil/s, {capacity_rps:.1f} requests/s "
+        f"({time.perf_counter() - t0:.1f} s)")
+    loads = []
+    for rho in rhos:
+        # Poisson arrivals at rho * capacity
+        t0 = time.perf_counter()
+        rng = np.random.default_rng((seed, int(rho * 1000)))
+        gaps = rng.exponential(1.0 / (rho * capacity_rps), size=len(mix))
+        arrivals = np.cumsum(gaps) - gaps[0]
+        stamps, st = serve(list(arrivals))
+        lat = np.array([s[3] - s[0] for s in stamps])
+        span = max(s[3] for s in stamps) - min(s[0] for s in stamps)
+        loads.append({"offered_load": rho,
+                      "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 2),
+                      "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 2),
+                      "throughput_GStencil_s": round(total_updates / span / 1e9, 2),
+                      "chunks": int(st["chunks"])})
+        log(f"serving: load {rho}: {loads[-1]} ({time.perf_counter() - t0:.1f} s)")
     alone_s = one_at_a_time(None)
     plain_s = one_at_a_time("method=plain")
-    capacity = total_updates / makespan / 1e9
     return {
-        "requests": len(mix), "offered_load": rho,
-        "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 2),
-        "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 2),
-        "throughput_GStencil_s": round(total_updates / span / 1e9, 2),
+        "requests": len(mix),
+        "loads": loads,
         "capacity_GStencil_s": round(capacity, 2),
         "sequential_alone_GStencil_s": round(total_updates / alone_s / 1e9, 2),
         "sequential_plain_GStencil_s": round(total_updates / plain_s / 1e9, 2),
         "capacity_vs_plain": round(capacity / (total_updates / plain_s / 1e9), 3),
+        "capacity_vs_alone": round(capacity / (total_updates / alone_s / 1e9), 3),
         "device_busy_frac": round(st_cap["busy_seconds"] / makespan, 3),
-        "chunks": int(st["chunks"]),
-        "mix": f"Poisson stream, seed {seed}: 1D 3-point / 2D 5- or 9-point / 3D 7-point "
-               f"Jacobi and 2D 5-point Gauss-Seidel; 2D sides log-uniform {side2d[0]}.."
-               f"{side2d[1]}, 3D {side3d[0]}..{side3d[1]}, 1D {n1d[0]:g}..{n1d[1]:g}, "
-               f"T uniform {steps[0]}..{steps[1]}, FP32/FP64 50/50; host input and output "
-               f"included in every form (the full mix scaled down to fit a benchmark run)",
+        "hbm_budget_GiB": budget / 2**30,
+        "mix": f"Poisson stream, seed {seed}, the first {len(mix)} requests of the serving "
+               f"mix: 1D 3-point / 2D 5- or 9-point / 3D 7-point Jacobi and 2D 5-point "
+               f"Gauss-Seidel; 2D sides log-uniform {side2d[0]}..{side2d[1]}, 3D "
+               f"{side3d[0]}..{side3d[1]}, 1D {n1d[0]:g}..{n1d[1]:g}, T uniform "
+               f"{steps[0]}..{steps[1]}, FP32/FP64 50/50; host input and output included "
+               f"in every form",
     }
 
 
@@ -441,11 +465,12 @@ def lcs_bench(torch, tvs, inputs, args, copy_gbs):
 
 
 def varcoef_bench(torch, tvs, inputs, args, copy_gbs):
-    """1D variable-coefficient Jacobi (a weight per point and offset), 1e5
-    points x 1000 steps: the time-skewed pipeline with the weights staged in
-    LDS against plain steps reading them from memory."""
+    """Variable-coefficient Jacobi (a weight per point and offset): 1D 1e5
+    points x 1000 steps (the time-skewed pipeline with the weights staged in
+    LDS) or 2D 4096^2 x 1000 steps (the band kernel reading each weight per
+    term), against plain steps reading them from memory."""
     import oracle
-    p = inputs.vc1d3p(**_kw(args.n, args.T))
+    p = (inputs.vc1d3p if args.workload == "vc1d3p" else inputs.vc2d5p)(**_kw(args.n, args.T))
     u0 = inputs.make_grid(p)
     W = inputs.varcoef_weights(p)
     grid = torch.from_numpy(u0).to("cuda")
@@ -459,6 +484,9 @@ def varcoef_bench(torch, tvs, inputs, args, copy_gbs):
     nu = p.updated_points()
     value = nu * p.T / (ms / 1e3) / 1e9
     k = info["k"]
+    if p.ndim >= 2:
+        # the band depth the 2D/3D band kernel takes with 4 points per lane
+        k = min(k, 8)
     band_ms = time_runs(torch, lambda: plan.run_varcoef(grid, w, 2 * k), 10) / 2
     ops = nu * k * (2 * p.order - 1)
     achieved = ops / (band_ms / 1e3) / 1e12
@@ -472,9 +500,15 @@ def varcoef_bench(torch, tvs, inputs, args, copy_gbs):
         "metric": METRIC, "value": round(value, 2), "unit": "GStencil/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
-        "data": f"synthetic: uniform[0,1) grid, diffusivity uniform[0.1,0.4], PCG64(seed {p.seed})",
-        "config": {"workload": f"1D 3-point Jacobi with variable coefficients {p.dims[0]} FP64, "
-                               f"T={p.T}, fixed ends, weights (a, 1-2a, a) per point",
+        "data": (f"synthetic: uniform[0,1) grid, diffusivity uniform[0.1,0.4], PCG64(seed {p.seed})"
+                 if p.ndim == 1 else f"synthetic: uniform[0,1) grid, diffusivity uniform"
+                                     f"[0.05,0.2], PCG64(seed {p.seed})"),
+        "config": {"workload": (f"1D 3-point Jacobi with variable coefficients {p.dims[0]} FP64, "
+                                f"T={p.T}, fixed ends, weights (a, 1-2a, a) per point"
+                                if p.ndim == 1 else
+                                f"2D 5-point Jacobi with variable coefficients "
+                                f"{p.dims[0]}x{p.dims[1]} FP64, T={p.T}, zero Dirichlet border, "
+                                f"weights (a, a, 1-4a, a, a) per point"),
                    "schedule": plan.tuning(), "updated_points": nu},
         "copy_GBs": round(copy_gbs, 1),
         "plain_sweep": {"value": round(plain_value, 2), "unit": "GStencil/s",
@@ -482,7 +516,8 @@ def varcoef_bench(torch, tvs, inputs, args, copy_gbs):
         "roofline": {"bound": "alu", "achieved": round(achieved, 3),
                      "peak": round(ALU_PEAK_TOPS, 2), "unit": "TFLOP/s",
                      "frac": round(achieved / ALU_PEAK_TOPS, 4), "traffic": None,
-                     "kernel": "tstp1d_r with LDS-staged weights (one launch of k steps)",
+                     "kernel": ("tstp1d_r with LDS-staged weights" if p.ndim == 1 else
+                                "tstp_ndr with weights read per term") + " (one launch of k steps)",
                      "kernel_ms": round(band_ms, 4),
                      "algorithmic_bytes": (2 + p.order) * 8 * nu},
     }
@@ -510,7 +545,10 @@ def main():
     ap.add_argument("--plain-steps", type=int, default=2, help="timed solves of the plain sweep")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
-    ap.add_argument("--serve-requests", type=int, default=200)
+    ap.add_argument("--serve-requests", type=int, default=300,
+                    help="requests of the serving mix per load level (the full stream is 2000)")
+    ap.add_argument("--serve-loads", default="0.5,0.8,1.0",
+                    help="offered loads, as fractions of the measured capacity")
     ap.add_argument("--workload", default="box2d9p", choices=sorted(WORKLOADS),
                     help="problem to time (default: the headline 2D 9-point box FP64)")
     ap.add_argument("--n", type=int, default=None, help="grid side (default: the workload's)")
@@ -544,7 +582,7 @@ def main():
     if args.workload == "lcs":
         print(json.dumps(lcs_bench(torch, tvs, inputs, args, copy_gbs)), flush=True)
         return
-    if args.workload == "vc1d3p":
+    if args.workload in ("vc1d3p", "vc2d5p"):
         print(json.dumps(varcoef_bench(torch, tvs, inputs, args, copy_gbs)), flush=True)
         return
     p = WORKLOADS[args.workload][0](inputs, args.n, args.T)
@@ -596,7 +634,8 @@ def main():
     # its redundant halo and pipeline-fill work and its shared products
     # (band_work); the other kernels count P products + (P - 1) sums per
     # update (Life: its integer operations)
-    nd_band = info["method"] == 1 and p.ndim >= 2 and p.dependence == inputs.JACOBI
+    nd_band = (info["method"] == 1 and p.ndim >= 2 and p.dependence == inputs.JACOBI and
+               info["radius"] == 1)
     if nd_band:
         uniform = len({np.float64(c).tobytes() for c in p.coeffs}) == 1
         computed, exec_ops = band_work(p, info, inputs, uniform)
@@ -673,7 +712,8 @@ def main():
     }
     if not args.no_serve and args.workload == "box2d9p":
         t0 = time.perf_counter()
-        out["serving"] = serving_run(torch, tvs, inputs, args.serve_requests, 0.8)
+        out["serving"] = serving_run(torch, tvs, inputs, args.serve_requests,
+                                     [float(x) for x in args.serve_loads.split(",")])
         log(f"serving: {out['serving']} ({time.perf_counter() - t0:.1f} s)")
         t0 = time.perf_counter()
         out["batch"] = batch_measure(torch, tvs, inputs)

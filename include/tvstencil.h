@@ -200,8 +200,11 @@ int stencil_plan_check(tvs_plan *plan);
  *   weights  device, P * N elements of the plan's dtype (F32 or F64); read
  *            only, not retained
  * Jacobi plans only (Gauss-Seidel: TVS_E_UNSUPPORTED; Life: TVS_E_INVALID).
- * 1D plans with a time-skewed schedule run bands of up to 64 levels with the
- * weights staged in LDS; 2D and 3D plans run one step per launch.
+ * Plans with a time-skewed schedule run bands of k levels: 1D with the
+ * weights staged in LDS (up to 64 levels), 2D and 3D (radius 1 and 2) on the
+ * plan's tile shape with 4 points per lane, each weight read by the level
+ * that forms its term; 3D radius 3 and plain schedules run one step per
+ * launch.
  */
 int stencil_run_varcoef(tvs_plan *plan, void *grid, const void *weights, int64_t T, void *stream);
 
@@ -218,13 +221,22 @@ int stencil_run_simple(void *grid, int ndim, const int64_t *dims, int dtype, con
                        void *stream);
 
 /*
- * Run n independent problems in persistent launches on one stream.  Each
- * plans[i] must be a Jacobi plan (Gauss-Seidel plans run through their own
- * persistent kernel and are accepted as well); grids[i], coeffs[i], T[i] as
- * in stencil_run.  A plan or a grid may appear at most once among the members
- * with T[i] > 0 (TVS_E_INVALID): members run at the same time.  Every result is bit-identical to stencil_run of the same
- * problem alone.  The launch sequence is captured once in a hipGraph per
- * distinct batch layout and replayed.
+ * Run n independent problems on one stream.  The Jacobi members of one
+ * kernel variant (precision, dimension, shape, boundary, points per lane) run
+ * in one persistent launch: every band of every such grid is cut into tiles,
+ * workgroups take tiles from a work list in band order, and a tile waits
+ * only until its grid's previous band is complete.  Each member keeps its
+ * plan's schedule (depth, tile shape, segment length, lane map; a plan whose
+ * schedule the batch kernels cannot take, e.g. plain steps, runs a default
+ * time-skewed one).  Gauss-Seidel plans run through their own persistent
+ * kernel, next to the Jacobi launches.  grids[i], coeffs[i], T[i] as in
+ * stencil_run.  A plan or a grid may appear at most once among the members
+ * with T[i] > 0 (TVS_E_INVALID): members run at the same time.  Radius > 1
+ * and Game of Life plans are not taken (TVS_E_UNSUPPORTED).  Every result is
+ * bit-identical to stencil_run of the same problem alone.  The launch
+ * sequence is captured once in a hipGraph per distinct batch layout and
+ * replayed.  A persistent launch whose bounded wait expires (results
+ * invalid) is reported by the next call (TVS_E_DEVICE).
  */
 int stencil_batch_run(int n, tvs_plan *const *plans, void *const *grids,
                       const double *const *coeffs, const int64_t *T, void *stream);

@@ -104,7 +104,7 @@ int enqueue_jacobi(tvs_plan* p, void* grid, const CoeffBuf& cb, int64_t T, hipSt
                 done += kb;
                 continue;
             }
-            if (pr.radius > 1)
+            if (pr.radius > 1 && pr.ndim == 1)
                 TVS_HIP_TRY(launch_tstp1d_radius(pr, g, buf[cur], buf[1 - cur], cb.bytes, st));
             else
                 TVS_HIP_TRY(launch_tstp_band(pr, g, buf[cur], buf[1 - cur], cb.bytes, st));
@@ -245,6 +245,10 @@ int make_plan(tvs_plan** out, const Problem& pr, const char* tuning) {
         Schedule t = s;
         rc = parse_tuning(tuning, &t, &has_method);
         if (rc) return rc;
+        // the skew follows from the radius unless the tuning names one
+        if (t.method == TVS_METHOD_TSTP && pr.dependence == TVS_JACOBI &&
+            std::strstr(tuning, "s=") == nullptr)
+            t.s = pr.radius == 1 ? 2 : pr.ndim == 1 ? pr.radius + 1 : 2 * pr.radius;
         if (t.method == TVS_METHOD_TSTP && pr.ndim >= 2 && pr.dependence == TVS_JACOBI &&
             std::strstr(tuning, "l=") == nullptr)
             choose_segment(pr, &t);
@@ -425,17 +429,32 @@ int stencil_run_varcoef(tvs_plan* p, void* grid, const void* weights, int64_t T,
     hipStream_t st = (hipStream_t)stream;
     void* buf[2] = {grid, p->scratch};
     int cur = 0;
-    // 1D time-skewed schedules run bands of up to k levels (64-lane
-    // pipelines); everything else, and a band whose weights do not fit LDS,
-    // runs plain steps
-    const bool band = pr.ndim == 1 && p->sched.method == TVS_METHOD_TSTP;
-    const int k = std::max(1, std::min(64, p->sched.k));
+    // Time-skewed schedules run bands of k levels: in 1D the 64-lane
+    // pipelines with the weights staged in LDS, in 2D and 3D the band kernel
+    // with the weights read per term.  Plain schedules, and bands the
+    // schedule's tile shape cannot take, run plain steps.
+    const bool band = p->sched.method == TVS_METHOD_TSTP;
+    int k = pr.ndim == 1 ? std::max(1, std::min(64, p->sched.k)) : std::max(1, p->sched.k);
+    // 2D/3D: the plan's tile shape with 4 points per lane (the band kernel
+    // with weights per term takes no more), as deep as the tile allows
+    Schedule vs = p->sched;
+    if (pr.ndim >= 2 && band) {
+        if (vs.c > 4) vs.c = 4;
+        BandGeom probe;
+        while (k > 1 && !ndr_geometry(pr, vs, k, &probe, true)) --k;
+    }
     const int Lv = p->sched.l > 0 ? p->sched.l : 256;
+    CoeffBuf none;
+    std::memset(none.bytes, 0, sizeof none.bytes);
     int64_t done = 0;
     while (done < T) {
         const int kb = (int)std::min<int64_t>(band ? k : 1, T - done);
-        if (band && tstp1d_vc_lds_bytes(pr, kb, Lv) <= 160 * 1024) {
+        BandGeom g;
+        if (band && pr.ndim == 1 && tstp1d_vc_lds_bytes(pr, kb, Lv) <= 160 * 1024) {
             TVS_HIP_TRY(launch_tstp1d_varcoef(pr, kb, Lv, buf[cur], buf[1 - cur], weights, st));
+            cur ^= 1;
+        } else if (band && pr.ndim >= 2 && ndr_geometry(pr, vs, kb, &g, true)) {
+            TVS_HIP_TRY(launch_tstp_ndr(pr, g, buf[cur], buf[1 - cur], none.bytes, weights, st));
             cur ^= 1;
         } else {
             for (int t = 0; t < kb; ++t) {

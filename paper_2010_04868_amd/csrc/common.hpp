@@ -122,6 +122,45 @@ struct Stencil {
     }
 };
 
+// Canonical offsets of radius R: the vectors of {-R..R}^D (star: at most one
+// non-zero component) in lexicographic order, axis 0 most significant.
+template <int D, bool BOX, int R>
+struct StencilR {
+    static constexpr int side = 2 * R + 1;
+    static constexpr int P = BOX ? (D == 1 ? side : D == 2 ? side * side : side * side * side)
+                                 : 2 * D * R + 1;
+    static constexpr int off(int q, int a) {
+        int total = 1;
+        for (int i = 0; i < D; ++i) total *= side;
+        int seen = 0;
+        for (int lin = 0; lin < total; ++lin) {
+            int d[3] = {0, 0, 0};
+            int rem = lin, nz = 0;
+            for (int i = D - 1; i >= 0; --i) {
+                d[i] = rem % side - R;
+                rem /= side;
+                nz += d[i] != 0;
+            }
+            if (!BOX && nz > 1) continue;
+            if (seen == q) return d[a];
+            ++seen;
+        }
+        return 0;
+    }
+    // first and one-past-last canonical index whose axis-0 offset is d0: the
+    // offsets of one axis-0 offset are a contiguous run of the order
+    static constexpr int group_begin(int d0) {
+        for (int q = 0; q < P; ++q)
+            if (off(q, 0) == d0) return q;
+        return P;
+    }
+    static constexpr int group_end(int d0) {
+        int e = group_begin(d0);
+        while (e < P && off(e, 0) == d0) ++e;
+        return e;
+    }
+};
+
 // Compile-time loop: f(std::integral_constant<int, I>) for I in [B, E).
 template <int B, int E, typename F>
 __host__ __device__ __forceinline__ void static_for(F&& f) {

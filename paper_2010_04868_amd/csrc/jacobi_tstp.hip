@@ -20,6 +20,7 @@ bool same_weight_bits(const double* c, int n) {
 }
 
 bool band_geometry(const Problem& p, const Schedule& s, int k, BandGeom* g) {
+    if (p.ndim >= 2 && p.radius > 1) return ndr_geometry(p, s, k, g);
     BandGeom r;
     r.k = k;
     r.lanemap = s.lanemap;
@@ -71,6 +72,7 @@ bool band_geometry(const Problem& p, const Schedule& s, int k, BandGeom* g) {
 hipError_t launch_tstp_band(const Problem& p, const BandGeom& g, const void* in, void* out,
                             const void* coeffs, hipStream_t st) {
     if (p.ndim == 1) return launch_tstp1d(p, g, in, out, coeffs, st);
+    if (p.radius > 1) return launch_tstp_ndr(p, g, in, out, coeffs, nullptr, st);
     if (p.rule == TVS_RULE_LIFE)
         return launch_nd_life_2d(p, g, (const uint32_t*)in, (uint32_t*)out, st);
     if (p.dtype == TVS_F64) {

@@ -40,6 +40,14 @@ bool band_geometry(const Problem& p, const Schedule& s, int k, BandGeom* g);
 hipError_t launch_tstp_band(const Problem& p, const BandGeom& g, const void* in, void* out,
                             const void* coeffs, hipStream_t st);
 
+// The 2D/3D band kernel for radius 1..3 with constant weights (radius > 1)
+// or variable coefficients (wts != nullptr: P weight planes of the grid's
+// size, offset-major): geometry of a band of k levels (vc: for variable
+// coefficients), and one band.
+bool ndr_geometry(const Problem& p, const Schedule& s, int k, BandGeom* g, bool vc = false);
+hipError_t launch_tstp_ndr(const Problem& p, const BandGeom& g, const void* in, void* out,
+                           const void* coeffs, const void* wts, hipStream_t st);
+
 // Gauss-Seidel.  `work` is device scratch of gs_work_bytes(p) bytes whose
 // first gs_state_bytes(p) bytes are zero before its first launch.  A run is
 // gs_layout_in (interior rows of grid -> band layout in work), launch_gs

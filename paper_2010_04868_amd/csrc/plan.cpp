@@ -174,7 +174,7 @@ double band_cost(const Problem& p, const BandGeom& g) {
     const double slots = (double)cus * wgs_per_cu(g);
     const double tiles = (double)g.blocks();
     const double rounds = std::ceil(tiles / slots);
-    const double steps = g.Lv + 3.0 * g.k;
+    const double steps = g.Lv + 3.0 * g.k * p.radius;
     return rounds * steps;
 }
 
@@ -220,13 +220,36 @@ Schedule default_schedule(const Problem& p) {
         return s;
     }
     const bool f64 = p.dtype == TVS_F64;
-    if (p.radius > 1) {
-        // radius > 1: the 1D pipeline (skew r + 1); 2D and 3D run plain steps
-        if (p.ndim != 1) {
+    if (p.radius > 1 && p.ndim >= 2) {
+        // the 2D/3D band kernel of radius r (skew 2r): R + 1 LDS rows per
+        // level and 2r halo columns per level limit the depth
+        s.s = 2 * p.radius;
+        s.c = 4;
+        s.lanemap = 1;
+        if (p.ndim == 2) {
+            s.k = 4;
+            s.w = 256;
+            while (s.w > 64 && s.w - 2 * s.k * p.radius > 2 * p.dims[1]) s.w /= 2;
+        } else {
+            s.k = 2;
+            s.w = 32;
+            s.h = 32;
+            while (s.w > 16 && s.w - 2 * s.k * p.radius > 2 * p.dims[2]) s.w /= 2;
+            while (s.h > 8 && s.h - 2 * s.k * p.radius > 2 * p.dims[1]) s.h /= 2;
+        }
+        while (s.k > 1 && (s.w <= 2 * s.k * p.radius || (p.ndim == 3 && s.h <= 2 * s.k * p.radius)))
+            --s.k;
+        choose_segment(p, &s);
+        BandGeom g;
+        if (!band_geometry(p, s, s.k, &g)) {
             Schedule plain;
             plain.method = TVS_METHOD_PLAIN;
             return plain;
         }
+        return s;
+    }
+    if (p.radius > 1) {
+        // radius > 1 in 1D: the 64-lane pipeline (skew r + 1)
         s.s = p.radius + 1;
         s.pl = 64;
         s.k = 64;
@@ -295,10 +318,12 @@ int check_schedule(const Problem& p, const Schedule& s) {
             return set_error(TVS_E_INVALID, "c (rows per lane) must be 1 for Gauss-Seidel");
         return TVS_OK;
     }
-    if (p.radius > 1) {
-        if (p.ndim != 1)
-            return set_error(TVS_E_INVALID, "the time-skewed pipeline for radius > 1 is 1D only; "
-                                            "use method=plain");
+    if (p.radius > 1 && p.ndim >= 2) {
+        if (s.s != 2 * p.radius)
+            return set_error(TVS_E_INVALID, "skew s = 2r: the 2D/3D pipeline of radius r runs "
+                                            "every level 2r stream rows behind the one below "
+                                            "(legal: s > r)");
+    } else if (p.radius > 1) {
         if (s.s != p.radius + 1)
             return set_error(TVS_E_INVALID, "skew s = r + 1 is the legal choice for radius r "
                                             "(s > max dx/dt)");

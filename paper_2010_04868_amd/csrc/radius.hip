@@ -21,33 +21,6 @@
 namespace tvs {
 namespace {
 
-// Canonical offsets of radius R: the vectors of {-R..R}^D (star: at most one
-// non-zero component) in lexicographic order, axis 0 most significant.
-template <int D, bool BOX, int R>
-struct StencilR {
-    static constexpr int side = 2 * R + 1;
-    static constexpr int P = BOX ? (D == 1 ? side : D == 2 ? side * side : side * side * side)
-                                 : 2 * D * R + 1;
-    static constexpr int off(int q, int a) {
-        int total = 1;
-        for (int i = 0; i < D; ++i) total *= side;
-        int seen = 0;
-        for (int lin = 0; lin < total; ++lin) {
-            int d[3] = {0, 0, 0};
-            int rem = lin, nz = 0;
-            for (int i = D - 1; i >= 0; --i) {
-                d[i] = rem % side - R;
-                rem /= side;
-                nz += d[i] != 0;
-            }
-            if (!BOX && nz > 1) continue;
-            if (seen == q) return d[a];
-            ++seen;
-        }
-        return 0;
-    }
-};
-
 __device__ __forceinline__ int64_t wrap64(int64_t i, int64_t n) {
     return i < 0 ? i + n : (i >= n ? i - n : i);
 }

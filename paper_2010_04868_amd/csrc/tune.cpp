@@ -109,6 +109,19 @@ std::vector<Schedule> tune_candidates(const Problem& p) {
                     s.l = l;
                     add(s);
                 }
+    } else if (p.ndim == 2 && p.radius > 1) {
+        for (int c : {4, 8})
+            for (int k : {1, 2, 3, 4, 6, 8})
+                for (int w : {64, 128, 256, 512})
+                    for (int lm : {0, 1}) {
+                        Schedule s = base;
+                        s.c = c;
+                        s.k = k;
+                        s.w = w;
+                        s.lanemap = lm;
+                        s.l = 0;
+                        add(s);
+                    }
     } else if (p.ndim == 2) {
         for (int c : {4, 8, 16})
             for (int k : {4, 6, 8, 12, 16})

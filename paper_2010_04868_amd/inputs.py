@@ -66,7 +66,11 @@ class Problem:
 
     @property
     def radius(self) -> int:
-        return 1
+        """r from the point count: star P = 2 d r + 1, box P = (2r + 1)^d."""
+        if self.shape == STAR:
+            return (self.order - 1) // (2 * self.ndim)
+        side = int(round(self.order ** (1.0 / self.ndim)))
+        return (side - 1) // 2
 
     def updated_points(self) -> int:
         """Points written per step (GStencil/s counts only these)."""
@@ -114,7 +118,7 @@ def life_board(dims: Sequence[int], seed, density: float = 0.5,
 def make_grid(p: Problem) -> np.ndarray:
     if p.dtype == I32:
         return life_board(p.dims, p.seed, 0.5, p.zero_border)
-    return uniform_grid(p.dims, p.dtype, p.seed, p.zero_border)
+    return uniform_grid(p.dims, p.dtype, p.seed, p.zero_border, p.radius)
 
 
 def star_coeffs(ndim: int, centre: float, neighbour: float) -> Tuple[float, ...]:
@@ -153,11 +157,32 @@ def vc1d3p(n: int = 100000, T: int = 1000) -> Problem:
 
 
 def varcoef_weights(p: Problem) -> np.ndarray:
-    """Weights of shape (3, n) for vc1d3p, drawn after the grid from
-    PCG64((seed, 1))."""
+    """Weights of shape (P,) + dims for the variable-coefficient workloads,
+    drawn after the grid from PCG64((seed, 1)): vc1d3p (a, 1 - 2a, a) with a
+    uniform in [0.1, 0.4]; vc2d5p (a, a, 1 - 4a, a, a) with a uniform in
+    [0.05, 0.2] (canonical order N, W, C, E, S)."""
     rng = np.random.Generator(np.random.PCG64((p.seed, 1)))
-    a = rng.uniform(0.1, 0.4, size=p.dims[0])
-    return np.stack([a, 1.0 - 2.0 * a, a]).astype(_NP[p.dtype])
+    if p.ndim == 1:
+        a = rng.uniform(0.1, 0.4, size=p.dims[0])
+        return np.stack([a, 1.0 - 2.0 * a, a]).astype(_NP[p.dtype])
+    a = rng.uniform(0.05, 0.2, size=p.dims)
+    return np.stack([a, a, 1.0 - 4.0 * a, a, a]).astype(_NP[p.dtype])
+
+
+def vc2d5p(n: int = 4096, T: int = 1000) -> Problem:
+    """2D 5-point Jacobi with variable coefficients (a heat equation with a
+    diffusivity per point): weights (a, a, 1 - 4a, a, a), a uniform in
+    [0.05, 0.2] from varcoef_weights; zero Dirichlet border."""
+    return Problem("vc2d5p", (n, n), F64, STAR, 5, JACOBI, DIRICHLET, (), T, 14,
+                   zero_border=True)
+
+
+def star2d9p(n: int = 8192, T: int = 1000) -> Problem:
+    """2D 9-point star of radius 2, weights 0.05 / 0.1 at distance 2 / 1 and
+    0.4 at the centre (canonical order (-2,0), (-1,0), (0,-2), (0,-1), (0,0),
+    (0,1), (0,2), (1,0), (2,0)), zero Dirichlet border two points deep."""
+    return Problem("star2d9p", (n, n), F64, STAR, 9, JACOBI, DIRICHLET,
+                   (0.05, 0.1, 0.05, 0.1, 0.4, 0.1, 0.05, 0.1, 0.05), T, 13, zero_border=True)
 
 
 def gs1d3p(n: int = 100000, T: int = 1000) -> Problem:

@@ -127,14 +127,24 @@ def test_radius_plans_without_device():
     p = tvs.Plan((1000,), F64, STAR, 5)              # radius 2: the 1D pipeline, skew 3
     inf = p.info()
     assert inf["radius"] == 2 and inf["method"] == 1 and inf["s"] == 3 and inf["pl"] == 64
-    assert tvs.Plan((50, 60), F64, BOX, 25).info()["method"] == 0      # 2D radius 2: plain
-    assert tvs.Plan((9, 9, 9), F32, STAR, 19).info()["radius"] == 3     # 3D radius 3 star
+    # 2D and 3D radius 2: the band kernel with skew 2r
+    b = tvs.Plan((500, 600), F64, BOX, 25).info()
+    assert b["method"] == 1 and b["s"] == 4 and b["radius"] == 2
+    assert tvs.Plan((50, 60, 70), F64, STAR, 13).info()["s"] == 4
+    t = tvs.Plan((500, 600), F32, STAR, 13, tuning="method=tstp,k=3,w=64,c=4,l=20").info()
+    assert (t["k"], t["s"], t["tile_w"], t["lane_c"], t["tile_l"]) == (3, 6, 64, 4, 20)
+    r3 = tvs.Plan((9, 9, 9), F32, STAR, 19).info()                  # 3D radius 3: plain steps
+    assert r3["radius"] == 3 and r3["method"] == 0
+    for bad in ("method=tstp,k=4,w=64,c=4,s=3",                      # the skew is 2r
+                "method=tstp,k=8,w=32,c=4",                          # 2kr halo columns >= w
+                "method=tstp,k=2,w=64,c=16"):                        # 4 or 8 points per lane
+        assert code_of(lambda: tvs.Plan((50, 60), F64, STAR, 9, tuning=bad)) == E["TVS_E_INVALID"]
+    assert code_of(lambda: tvs.Plan((9, 9, 9), F64, STAR, 19, tuning="method=tstp,k=1,w=16,h=16,c=4")) \
+        == E["TVS_E_INVALID"]
     q = tvs.Plan((1000,), F64, STAR, 7, tuning="method=tstp,k=16,l=100")
     assert q.info()["k"] == 16 and q.info()["s"] == 4
     for bad in ("method=tstp,k=8,l=64,pl=16", "method=tstp,k=8,s=2", "method=tstp,k=8,l=4000"):
         assert code_of(lambda: tvs.Plan((1000,), F64, STAR, 5, tuning=bad)) == E["TVS_E_INVALID"]
-    assert code_of(lambda: tvs.Plan((50, 60), F64, STAR, 9, tuning="method=tstp,k=4")) \
-        == E["TVS_E_INVALID"]
     lib = _lib.load()
     P = (ctypes.c_void_p * 1)(p.handle.value)
     G = (ctypes.c_void_p * 1)(0x1000)

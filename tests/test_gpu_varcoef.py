@@ -2,8 +2,9 @@
 per point, fixed over time): bit-exact against the oracle's variable-
 coefficient sweep (FP64, and FP32 against its FP32 mirror).  1D runs the
 time-skewed pipeline at several depths and segment lengths; 2D and 3D run
-plain steps.  Weights are distinct per point and offset, so an offset or
-point mix-up shows."""
+the band kernel with the weights read per term (radius 1 and 2; 3D radius 3
+runs plain steps).  Weights are distinct per point and offset, so an offset
+or point mix-up shows."""
 import numpy as np
 import pytest
 
@@ -16,7 +17,13 @@ pytestmark = pytest.mark.gpu
 CASES = [((97,), STAR, 3), ((1000,), STAR, 3), ((4099,), STAR, 3), ((300,), STAR, 5),
          ((301,), STAR, 7), ((5,), STAR, 3), ((37, 53), STAR, 5), ((37, 53), BOX, 9),
          ((40, 41), STAR, 9), ((17, 19, 23), STAR, 7), ((9, 10, 11), BOX, 27),
-         ((11, 12, 13), STAR, 13)]
+         ((11, 12, 13), STAR, 13), ((70, 130), STAR, 5), ((66, 140), BOX, 9),
+         ((80, 150), STAR, 9), ((70, 140), BOX, 25), ((60, 130), STAR, 13),
+         ((20, 40, 44), STAR, 7), ((18, 36, 40), BOX, 27), ((24, 40, 44), STAR, 13),
+         ((12, 14, 16), STAR, 19)]
+BAND_TUNINGS = {2: ["method=tstp,k=2,w=32,c=4,l=16", "method=tstp,k=3,w=64,c=4,l=20,lanemap=0"],
+                3: ["method=tstp,k=1,w=16,h=16,c=4,l=8",
+                    "method=tstp,k=2,w=32,h=16,c=4,l=12,lanemap=1"]}
 
 
 def gpu_varcoef(u0, W, shape, order, boundary, T, tuning=None):
@@ -43,6 +50,8 @@ def test_varcoef_matches_oracle(boundary, dtype):
         tunings = [None, "method=plain"]
         if len(dims) == 1:
             tunings += ["method=tstp,k=1,l=16", "method=tstp,k=5,l=20", "method=tstp,k=64,l=100"]
+        elif not (len(dims) == 3 and P == 19):
+            tunings += BAND_TUNINGS[len(dims)]
         for T in (1, 2, 7, 70):
             ref = oracle.sweep_varcoef(u0, W, shape, boundary, T, P, precision=prec)
             for tuning in tunings:

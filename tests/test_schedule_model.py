@@ -100,28 +100,137 @@ def test_lds_pipeline_schedule(k, lin):
         assert (k, r) in produced
 
 
-def replay_register_pipeline(k, lin):
-    """Inside one lane: level j at step q emits row q-j from level j-1 row q-j+1."""
+def replay_radius_pipeline(k, lin, r):
+    """The 2D/3D band kernel of radius r (skew 2r): at step q, level j reads
+    row p = q + r - 2rj of level j-1 from LDS slot (q - r) mod (r + 1) and
+    emits row p - r into slot q mod (r + 1); level 0 row q enters slot
+    q mod (r + 1) at step q.  Checks that every row a valid point reads is
+    still in its slot when read (written at an earlier step, not yet
+    overwritten), that a row emitted at step q is read no earlier than step
+    q + 1, and that the running-sum ring slot (row mod 2r) a level uses for a
+    row is the same at every level for a given step parity class."""
+    slots = r + 1
+    lds = {}          # (level, slot) -> (row, step written)
     produced = {}
-    for q in range(lin):
-        produced[(0, q)] = (q, 0)
+    ring_slot = {}    # (q mod 2r, axis-0 offset) -> ring slot, must not depend on j
+    for q in range(lin + r * k + 1):
+        reads = []
         for j in range(1, k + 1):
-            r = q - j
-            if r < 0:
+            p = q + r - 2 * r * j
+            if p < 0 or p >= lin:
                 continue
-            for rr in (r - 1, r, r + 1):
-                if 0 <= rr < lin:
-                    assert produced[(j - 1, rr)] <= (q, j - 1)
-            assert (j, r) not in produced
-            produced[(j, r)] = (q, j)
+            # the point p - dd receives its terms of axis-0 offset dd
+            for dd in range(-r, r + 1):
+                key = (q % (2 * r), dd)
+                slot = (p - dd) % (2 * r)
+                assert ring_slot.setdefault(key, slot) == slot
+            reads.append((j, p))
+        writes = []
+        if q < lin:
+            writes.append((0, q))
+        for j in range(1, k + 1):
+            p = q + r - 2 * r * j
+            if 0 <= p < lin and p - r >= 0:
+                writes.append((j, p - r))
+        # reads of this step see the slots as left by earlier steps
+        for j, p in reads:
+            level_ok = j - 1 == 0 or (j - 1) * r <= p < lin - (j - 1) * r
+            # row p feeds points p - r .. p + r of level j; it must be right
+            # if any of them is a valid point of level j
+            need = any(j * r <= z < lin - j * r for z in range(p - r, p + r + 1))
+            if need:
+                assert level_ok
+                row, when = lds[(j - 1, (q - r) % slots)]
+                assert row == p and when < q
+        for lev, row in writes:
+            lds[(lev, q % slots)] = (row, q)
+            if lev > 0:
+                assert (lev, row) not in produced
+                produced[(lev, row)] = q
     return produced
 
 
-@pytest.mark.parametrize("k,lin", [(4, 20), (8, 37), (16, 70)])
-def test_register_pipeline_schedule(k, lin):
-    produced = replay_register_pipeline(k, lin)
-    for r in range(k, lin - k):
-        assert (k, r) in produced
+@pytest.mark.parametrize("k,lin,r", [(1, 9, 2), (3, 30, 2), (4, 41, 2), (2, 25, 3), (3, 40, 3),
+                                     (8, 40, 1)])
+def test_radius_pipeline_schedule(k, lin, r):
+    produced = replay_radius_pipeline(k, lin, r)
+    # every valid row of the top level is emitted
+    for row in range(k * r, lin - k * r):
+        assert (k, row) in produced
+
+
+def simulate_persistent_batch(tiles, workers, seed):
+    """The persistent batch launch: items in round-major ticket order (band b
+    of every grid before band b + 1 of any); a worker takes the next ticket,
+    waits until its grid's completed-tile counter reaches the tiles of all
+    earlier bands of that grid, runs the tile and bumps the counter.  Workers
+    advance in a random order (any interleaving the hardware may produce).
+    Returns the completion order; raises if no worker can advance (a
+    deadlock) before every item is done."""
+    import random
+    rnd = random.Random(seed)
+    items = []
+    prefix = []
+    for g, per_band in enumerate(tiles):
+        acc = [0]
+        for n in per_band:
+            acc.append(acc[-1] + n)
+        prefix.append(acc)
+    nb = max(len(t) for t in tiles)
+    for b in range(nb):
+        for g, per_band in enumerate(tiles):
+            if b < len(per_band):
+                items += [(g, b, t) for t in range(per_band[b])]
+    ticket = 0
+    done = [0] * len(tiles)
+    state = [None] * workers      # None: taking a ticket; else (item, phase)
+    finished = []
+    while len(finished) < len(items):
+        movable = []
+        for w in range(workers):
+            st = state[w]
+            if st is None:
+                if ticket < len(items):
+                    movable.append(w)
+            else:
+                (g, b, t), phase = st
+                if phase == "wait" and done[g] >= prefix[g][b]:
+                    movable.append(w)
+                elif phase == "run":
+                    movable.append(w)
+        assert movable, f"deadlock after {len(finished)} of {len(items)} items"
+        w = rnd.choice(movable)
+        st = state[w]
+        if st is None:
+            state[w] = (items[ticket], "wait")
+            ticket += 1
+        elif st[1] == "wait":
+            state[w] = (st[0], "run")
+        else:
+            g, b, t = st[0]
+            # everything this tile reads or overwrites belongs to bands < b,
+            # all complete
+            assert done[g] >= prefix[g][b]
+            done[g] += 1
+            finished.append(st[0])
+            state[w] = None
+    return finished
+
+
+@pytest.mark.parametrize("workers", [1, 2, 7, 64])
+@pytest.mark.parametrize("seed", range(5))
+def test_persistent_batch_drains(workers, seed):
+    import random
+    rnd = random.Random(100 + seed)
+    tiles = [[rnd.randint(1, 9)] * rnd.randint(1, 6) for _ in range(rnd.randint(1, 12))]
+    for per_band in tiles:      # a last band with fewer tiles, as a shallower band may have
+        per_band[-1] = max(1, per_band[-1] - rnd.randint(0, 2))
+    order = simulate_persistent_batch(tiles, workers, seed)
+    assert len(order) == sum(sum(t) for t in tiles)
+    # bands of one grid complete in order
+    for g in range(len(tiles)):
+        bands = [b for gg, b, _ in order if gg == g]
+        assert bands == sorted(bands)
 
 
 def replay_gs_wavefront(rows, cols, sigma):
