@@ -21,7 +21,8 @@ JACOBI, GAUSS_SEIDEL = 0, 1
 DIRICHLET, PERIODIC = 0, 1
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+# TVS_ORACLE_LIBRARY: a sanitized build of the same source (oracle/build.py)
+_LIB_PATH = os.environ.get("TVS_ORACLE_LIBRARY") or os.path.join(_HERE, "liboracle.so")
 _lib = None
 
 

@@ -12,14 +12,24 @@ CFLAGS = ["-std=c11", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-s
           "-Wall", "-Wextra"]
 
 
-def build(verbose: bool = False) -> str:
-    tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = ["gcc", *CFLAGS, os.path.join(HERE, "oracle.c"), "-o", tmp]
+def build(verbose: bool = False, sanitize: bool = False) -> str:
+    """sanitize: an AddressSanitizer + UndefinedBehaviorSanitizer copy in
+    _build/sanitize/ (built with clang so that it shares the runtime the
+    sanitized library uses)."""
+    if sanitize:
+        out = os.path.join(os.path.dirname(HERE), "_build", "sanitize", "liboracle.so")
+        os.makedirs(os.path.dirname(out), exist_ok=True)
+        cc = ["/opt/rocm/llvm/bin/clang", "-fsanitize=address,undefined", "-shared-libsan",
+              "-fno-omit-frame-pointer"]
+    else:
+        out, cc = LIB, ["gcc"]
+    tmp = out + ".tmp%d" % os.getpid()
+    cmd = [*cc, *CFLAGS, os.path.join(HERE, "oracle.c"), "-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, out)
+    return out
 
 
 if __name__ == "__main__":

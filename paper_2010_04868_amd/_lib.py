@@ -10,7 +10,8 @@ import ctypes
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libtvstencil.so")
+# TVS_LIBRARY: a host-sanitized build of the same sources (build.py --sanitize)
+LIB_PATH = os.environ.get("TVS_LIBRARY") or os.path.join(HERE, "libtvstencil.so")
 
 TVS_OK = 0
 ERRORS = {

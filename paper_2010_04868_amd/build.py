@@ -45,13 +45,22 @@ def _headers_mtime() -> float:
     return max(os.path.getmtime(h) for h in hs)
 
 
-def _compile(src: str, verbose: bool, newer_than: float = None) -> str:
-    obj = os.path.join(BUILD, os.path.basename(src) + ".o")
+# Host sanitizers (AddressSanitizer + UndefinedBehaviorSanitizer) for the
+# host side of the library: plan validation, tuning strings and cache, the
+# server's policy.  Device code is built as usual (no GPU sanitizer).
+SANITIZE = ("-Xarch_host -fsanitize=address -Xarch_host -fsanitize=undefined "
+            "-Xarch_host -fno-omit-frame-pointer -shared-libsan").split()
+SAN_BUILD = os.path.join(BUILD, "sanitize")
+SAN_LIB = os.path.join(SAN_BUILD, "libtvstencil.so")
+
+
+def _compile(src: str, verbose: bool, newer_than: float = None, sanitize: bool = False) -> str:
+    obj = os.path.join(SAN_BUILD if sanitize else BUILD, os.path.basename(src) + ".o")
     if newer_than is not None and os.path.exists(obj):
         t = os.path.getmtime(obj)
         if t > newer_than and t > os.path.getmtime(src):
             return obj
-    cmd = [HIPCC, *COMMON, "-c", src, "-o", obj]
+    cmd = [HIPCC, *COMMON, *(SANITIZE if sanitize else []), "-c", src, "-o", obj]
     if src.endswith(".cpp"):
         cmd[1:1] = ["-x", "hip"]
     if verbose:
@@ -66,25 +75,52 @@ def _compile(src: str, verbose: bool, newer_than: float = None) -> str:
     return obj
 
 
-def build(verbose: bool = False, jobs: int | None = None, incremental: bool = False) -> str:
+def build(verbose: bool = False, jobs: int | None = None, incremental: bool = False,
+          sanitize: bool = False) -> str:
     """Compile every source (incremental: only those older than their object
-    or than any header) and link the library."""
-    os.makedirs(BUILD, exist_ok=True)
+    or than any header) and link the library.  sanitize: a host-sanitized
+    copy in _build/sanitize/ instead (load it with the sanitizer runtime
+    preloaded; see sanitizer_env)."""
+    os.makedirs(SAN_BUILD if sanitize else BUILD, exist_ok=True)
     srcs = sources()
     jobs = jobs or min(8, len(srcs))
     newer = _headers_mtime() if incremental else None
     with cf.ThreadPoolExecutor(jobs) as ex:
-        objs = list(ex.map(lambda s: _compile(s, verbose, newer), srcs))
-    tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", *objs, "-o", tmp]
+        objs = list(ex.map(lambda s: _compile(s, verbose, newer, sanitize), srcs))
+    out = SAN_LIB if sanitize else LIB
+    tmp = out + ".tmp%d" % os.getpid()
+    cmd = [HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", *(SANITIZE if sanitize else []),
+           *objs, "-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed\n{r.stdout}\n{r.stderr}")
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, out)
+    return out
+
+
+def sanitizer_env() -> dict:
+    """Environment for running the CPU tests against the sanitized builds:
+    the sanitizer runtime preloaded, leak checks off (the interpreter's own
+    allocations are not this library's), both libraries redirected."""
+    rt = subprocess.run([HIPCC, "-print-file-name=libclang_rt.asan-x86_64.so"],
+                        capture_output=True, text=True).stdout.strip()
+    env = dict(os.environ)
+    env.update({"LD_PRELOAD": rt, "ASAN_OPTIONS": "detect_leaks=0:abort_on_error=1",
+                "UBSAN_OPTIONS": "print_stacktrace=1:halt_on_error=1",
+                "TVS_LIBRARY": SAN_LIB,
+                "TVS_ORACLE_LIBRARY": os.path.join(SAN_BUILD, "liboracle.so")})
+    return env
 
 
 if __name__ == "__main__":
+    if "--sanitize" in sys.argv:
+        # host-sanitized library and oracle, then the CPU test suite against them
+        print(build(verbose="-v" in sys.argv, incremental="-i" in sys.argv, sanitize=True))
+        sys.path.insert(0, ROOT)
+        from oracle import build as obuild
+        print(obuild.build(sanitize=True))
+        sys.exit(subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-m", "not gpu",
+                                 os.path.join(ROOT, "tests")], env=sanitizer_env()).returncode)
     print(build(verbose="-v" in sys.argv, incremental="-i" in sys.argv))
