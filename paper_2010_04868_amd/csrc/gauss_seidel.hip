@@ -53,6 +53,7 @@ constexpr int kBlock = 8;        // steps whose loads are issued together
 // trails its producer by about KS columns.  Wide rows take 128 (fewer
 // fences), narrow ones 32 (shorter trails where little else is in flight).
 constexpr long long kSpinLimit = 1ll << 22;  // ~seconds: far beyond any legitimate wait
+constexpr int kAllSteps = 1 << 30;            // progress of a finished item
 
 struct GsArgs {
     int n0, n1;
@@ -173,14 +174,31 @@ __global__ __launch_bounds__(64) void gs2d(T* grid, T* lay, GsArgs a, Coeffs<T> 
         const int* prog_south =
             (t > 0 && b + 1 < a.nb) ? a.progress + (t - 1) * a.nb + (b + 1) : nullptr;
 
-        // steps: row i of the band is at column c = u - 1 - SIG*i in [-1, ncols]
+        // steps: at step u, lane i updates column u - SIG*i (c = u - 1 - SIG*i
+        // in [-1, ncols]).  Progress is published as the number of steps an
+        // item has completed (kAllSteps once it is done).  Before an interval
+        // of steps [us, us+KS) an item waits, per producer, for exactly the
+        // steps whose values the interval reads:
+        //  * (b, t-1), the same band one sweep earlier: lane i reads the old
+        //    value of its own row at column u - SIG*i + 1 (written by that
+        //    item's lane i at its step u + 1) and of row i+1 (its lane i+1,
+        //    step u + 1 + SIG): at most us + KS + SIG + 1 steps;
+        //  * (b+1, t-1), the band below one sweep earlier: only the last lane
+        //    reads its first row, at column u - SIG*L + 1 (that item's lane 0,
+        //    step u - SIG*L + 1): us + KS + 1 - SIG*L steps, which is behind
+        //    this item's own position;
+        //  * (b-1, t), the band above in this sweep: lane 0 reads its last row
+        //    (lane 63) at column u - 1 + SIG, written at that item's step
+        //    u - 1 + SIG + 63*SIG: us + KS - 1 + 64*SIG steps.
+        // These also keep every overwrite behind the reads of the old values
+        // it replaces: (b-1, t) reads this band's first row, and (b+1, t-1)
+        // its last row, before this item overwrites them.
         const int U = a.ncols + 2 + SIG * L;
         for (int us = 0; us < U; us += KS) {
-          // columns the leading row (lane 0) reaches in this interval
-          const int cmax = us + KS - 2;
-          if (prog_prev) wait_at_least(prog_prev, min(a.ncols, cmax + 2), a.status);
-          if (prog_south) wait_at_least(prog_south, min(a.ncols, cmax + 2), a.status);
-          if (prog_north) wait_at_least(prog_north, min(a.ncols, cmax + SIG), a.status);
+          if (prog_prev) wait_at_least(prog_prev, us + KS + SIG + 1, a.status);
+          if (prog_south && us + KS + 1 - SIG * L > 0)
+              wait_at_least(prog_south, us + KS + 1 - SIG * L, a.status);
+          if (prog_north) wait_at_least(prog_north, us + KS - 1 + SIG * kRows, a.status);
           // the producers' rows written before their progress stores are visible now
           __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
           // An inner interval keeps every lane (idle ones included) on an
@@ -190,8 +208,11 @@ __global__ __launch_bounds__(64) void gs2d(T* grid, T* lay, GsArgs a, Coeffs<T> 
           const bool inner = us >= 1 + SIG * (kRows - 1) && us + KS <= a.ncols + 1;
           auto interval = [&](auto inner_t) {
             constexpr bool IN = decltype(inner_t)::value;
-            for (int u0 = us; u0 < us + KS && (IN || u0 < U); u0 += kBlock) {
-              T e_in[kBlock], se_in[kBlock], n_in[kBlock];
+            // The loads of a block of kBlock steps: east and south values of
+            // every lane's point and lane 0's north values.  They read only
+            // values the waits above cover, and old values no lane overwrites
+            // before the block's steps, so they may be issued a block early.
+            auto load_blk = [&](int u0, T (&e_in)[kBlock], T (&se_in)[kBlock], T (&n_in)[kBlock]) {
               // row below at column u0+1-SIG*lane, and lane 0's row above at
               // column u0-1+SIG (the same address in every lane)
               const T* bptr = lane < L ? band + (int64_t)(u0 + 1 + SIG) * kRows + lane + 1
@@ -222,6 +243,9 @@ __global__ __launch_bounds__(64) void gs2d(T* grid, T* lay, GsArgs a, Coeffs<T> 
                       n_in[m] = okn ? nv : T(0);
                   }
               }
+            };
+            auto comp_blk = [&](int u0, const T (&e_in)[kBlock], const T (&se_in)[kBlock],
+                                const T (&n_in)[kBlock]) {
 #pragma unroll
               for (int m = 0; m < kBlock; ++m) {
                   // value of the row above, one column ahead of where the row
@@ -269,19 +293,31 @@ __global__ __launch_bounds__(64) void gs2d(T* grid, T* lay, GsArgs a, Coeffs<T> 
                       out = r;
                   }
               }
+            };
+            // blocks of the interval (the last interval stops at U), the next
+            // block's loads in flight while a block computes
+            const int uend = IN ? us + KS : min(us + KS, U);
+            T eA[kBlock], seA[kBlock], nA[kBlock], eB[kBlock], seB[kBlock], nB[kBlock];
+            load_blk(us, eA, seA, nA);
+            for (int u0 = us; u0 < uend; u0 += 2 * kBlock) {
+              const bool hasB = u0 + kBlock < uend;
+              if (hasB) load_blk(u0 + kBlock, eB, seB, nB);
+              comp_blk(u0, eA, seA, nA);
+              if (!hasB) break;
+              if (u0 + 2 * kBlock < uend) load_blk(u0 + 2 * kBlock, eA, seA, nA);
+              comp_blk(u0 + kBlock, eB, seB, nB);
             }
           };
           if (inner)
               interval(std::true_type{});
           else
               interval(std::false_type{});
-          // publish the columns completed on the band's last row
-          const int done = min(a.ncols, max(0, us + KS - 1 - SIG * L));
+          // publish the steps completed
           __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-          __hip_atomic_store(prog_self, done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          __hip_atomic_store(prog_self, us + KS, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-        __hip_atomic_store(prog_self, a.ncols, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(prog_self, kAllSteps, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
 }
 

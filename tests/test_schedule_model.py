@@ -260,3 +260,112 @@ def replay_gs_wavefront(rows, cols, sigma):
 @pytest.mark.parametrize("sigma", [1, 2])
 def test_gauss_seidel_wavefront_order(sigma):
     replay_gs_wavefront(64, 50, sigma)
+
+
+def simulate_gs_items(nb, rows, ncols, sweeps, ks, sig, seed, last_rows=None):
+    """The 2D Gauss-Seidel item pipeline with its exact waits, at small size.
+
+    Items (band b, sweep t), bands of `rows` rows (the last band may have
+    fewer), run by independent workers in a random interleaving of single
+    steps.  At step u lane i of item (b, t) updates row 1 + rows*b + i at
+    column u - sig*i.  Before each interval of ks steps an item waits until
+    (b, t-1) has completed us + ks + sig + 1 steps, (b+1, t-1) us + ks + 1 -
+    sig*L steps (L its last lane) and (b-1, t) us + ks - 1 + sig*rows steps,
+    the kernel's thresholds with `rows` for 64.  Every value carries the
+    sweep that wrote it.  Checked: (1) when an interval starts, every value
+    any of its steps reads already has the sweep it must have (loads may be
+    issued anywhere in the interval); (2) no step overwrites a value some
+    later step of another item still has to read in its old sweep."""
+    import random
+    rnd = random.Random(seed)
+    nrow = 2 + rows * (nb - 1) + (last_rows if last_rows else rows)
+    ver = {(x, y): 0 for x in range(nrow) for y in range(ncols + 2)}
+    band_rows = [rows] * nb
+    if last_rows:
+        band_rows[-1] = last_rows
+    box = sig == 2
+
+    def reads(b, t, i, u):
+        """(point, sweep it must hold) read from memory by lane i of (b, t) at
+        step u.  The west value is the lane's own previous result and the
+        north values of lanes i > 0 come from lane i - 1 of the same item (a
+        lane shift): neither is read from memory."""
+        x = 1 + rows * b + i
+        y = u - sig * i
+        if not 1 <= y <= ncols:
+            return []
+        out = [((x, y), t - 1), ((x, y + 1), t - 1)]
+        cols = (y - 1, y, y + 1) if box else (y,)
+        if i == 0:
+            out += [((x - 1, c), t) for c in cols]
+        out += [((x + 1, c), t - 1) for c in cols]
+        return [((px, py), v) for (px, py), v in out
+                if 1 <= px <= nrow - 2 and 1 <= py <= ncols]   # borders never change
+
+    def steps_of(b):
+        return ncols + 2 + sig * (band_rows[b] - 1)
+
+    items = [(b, t) for t in range(1, sweeps + 1) for b in range(nb)]
+    done = {it: 0 for it in items}
+    FINISHED = 1 << 30
+    pos = {it: 0 for it in items}          # next step
+    pending = {}                           # (point, version) -> readers left
+    for b, t in items:
+        for u in range(steps_of(b)):
+            for i in range(band_rows[b]):
+                for pt, v in reads(b, t, i, u):
+                    if v == t - 1:
+                        pending[(pt, v)] = pending.get((pt, v), 0) + 1
+
+    def ready(it):
+        b, t = it
+        us = pos[it]
+        if us % ks:
+            return True
+        need = []
+        if t > 1:
+            need.append(((b, t - 1), us + ks + sig + 1))
+            if b + 1 < nb and us + ks + 1 - sig * (band_rows[b] - 1) > 0:
+                need.append(((b + 1, t - 1), us + ks + 1 - sig * (band_rows[b] - 1)))
+        if b > 0:
+            need.append(((b - 1, t), us + ks - 1 + sig * rows))
+        return all(done[p] >= n for p, n in need)
+
+    active = set(items)
+    started = set()
+    while active:
+        cand = [it for it in active if ready(it)]
+        assert cand, "deadlock"
+        it = rnd.choice(cand)
+        b, t = it
+        u = pos[it]
+        if u % ks == 0:
+            # interval start: everything the interval reads is in place
+            for uu in range(u, min(u + ks, steps_of(b))):
+                for i in range(band_rows[b]):
+                    for pt, v in reads(b, t, i, uu):
+                        assert ver[pt] == v, (it, uu, i, pt, ver[pt], v)
+        for i in range(band_rows[b]):
+            for pt, v in reads(b, t, i, u):
+                if v == t - 1:
+                    pending[(pt, v)] -= 1
+        for i in range(band_rows[b]):
+            x, y = 1 + rows * b + i, u - sig * i
+            if 1 <= y <= ncols:
+                assert pending.get(((x, y), t - 1), 0) == 0, ("overwrite before read", it, u, i)
+                ver[(x, y)] = t
+        pos[it] = u + 1
+        if pos[it] % ks == 0:
+            done[it] = pos[it]
+        if pos[it] >= steps_of(b):
+            done[it] = FINISHED
+            active.discard(it)
+    assert all(v == sweeps for (x, y), v in ver.items() if 1 <= x <= nrow - 2 and 1 <= y <= ncols)
+
+
+@pytest.mark.parametrize("sig", [1, 2])
+@pytest.mark.parametrize("ks,last_rows", [(2, None), (4, 3), (8, 1), (4, None)])
+@pytest.mark.parametrize("seed", range(3))
+def test_gauss_seidel_item_waits(sig, ks, last_rows, seed):
+    simulate_gs_items(nb=4, rows=5, ncols=13, sweeps=4, ks=ks, sig=sig, seed=seed,
+                      last_rows=last_rows)
