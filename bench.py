@@ -280,7 +280,7 @@ def serving_run(torch, tvs, inputs, n_req, rhos, seed=5, budget=4 << 30):
     total_updates = sum(r.problem.updated_points() * r.problem.T for r in mix)
 
     def serve(arrivals):
-        srv = tvs.Server(hbm_budget=budget, max_slots=64, chunk_steps=64)
+        srv = tvs.Server(hbm_budget=budget, max_slots=64, chunk_steps=0)
         try:
             t_base = time.perf_counter()
             ids = []
@@ -377,6 +377,12 @@ def batch_measure(torch, tvs, inputs, n_grids=48, seed=7, reps=3):
         return best
 
     t_batch = timed(lambda: tvs.batch_run(plans, dev, coeffs, Ts))
+    # the same batch as one persistent launch per kernel variant
+    os.environ["TVS_BATCH_PERSISTENT"] = "1"
+    try:
+        t_pers = timed(lambda: tvs.batch_run(plans, dev, coeffs, Ts))
+    finally:
+        del os.environ["TVS_BATCH_PERSISTENT"]
     t_alone = timed(lambda: [pl.run(g, c, T) for pl, g, c, T in zip(plans, dev, coeffs, Ts)])
     t_plain = timed(lambda: [pl.run(g, c, T) for pl, g, c, T in zip(plain, dev, coeffs, Ts)])
     for pl in plans + plain:
@@ -385,13 +391,15 @@ def batch_measure(torch, tvs, inputs, n_grids=48, seed=7, reps=3):
     return {
         "grids": len(probs), "gauss_seidel_grids": n_gs,
         "batch_GStencil_s": round(total / t_batch / 1e9, 2),
+        "persistent_launch_GStencil_s": round(total / t_pers / 1e9, 2),
         "sequential_alone_GStencil_s": round(total / t_alone / 1e9, 2),
         "sequential_plain_GStencil_s": round(total / t_plain / 1e9, 2),
         "batch_vs_plain": round(t_plain / t_batch, 3),
         "batch_vs_alone": round(t_alone / t_batch, 3),
         "mix": f"seed {seed}, the serving mix's kinds and sizes (2D sides {side2d[0]}..{side2d[1]}, "
                f"3D {side3d[0]}..{side3d[1]}, 1D {n1d[0]:g}..{n1d[1]:g}, T {steps[0]}..{steps[1]}); "
-               f"grids resident in HBM, default schedules, best of {reps}",
+               f"grids resident in HBM, each plan's default schedule, band-round launches "
+               f"(and one persistent launch per kernel variant), best of {reps}",
     }
 
 

@@ -1,13 +1,32 @@
 // Batched launches: many Jacobi grids of uneven shapes and step counts
 // advance together.
 //
-// A batch is cut into band rounds: round b runs band b of every grid that
-// still has one, as ONE kernel launch whose workgroups take (grid, tile)
-// items from a device-resident work list.  The kernel boundary between
-// rounds is the only synchronization a band needs (band b+1 reads what band
-// b wrote and overwrites what band b read), so there are no waits between
-// workgroups and nothing to deadlock.  The round sequence of a batch layout
-// that repeats is captured once in a hipGraph and replayed.
+// The grids of one kernel variant (precision, dimension, shape, boundary,
+// equal weights, points per lane) run together.  Every grid keeps the
+// schedule its plan was tuned to (depth, tile shape, segment length, lane
+// map); its bands are cut into tiles, and the work list holds every tile of
+// every band of every grid in round-major order (band b of every grid before
+// band b + 1 of any).  Band b reads what band b - 1 wrote and overwrites what
+// it read.  Two ways to run a group:
+//
+//   * round launches (the default): one launch per round b over the round's
+//     slice of the work list; the kernel boundary is the only
+//     synchronization, so there are no waits between workgroups;
+//   * one persistent launch (TVS_BATCH_PERSISTENT=1): workgroups take items
+//     from an atomic ticket, and a tile of band b of grid g waits until all
+//     tiles of the grid's earlier bands are done (a per-grid counter of
+//     finished tiles).  Every wait points to an earlier ticket, held by a
+//     workgroup that is running and never waits for a later one, so the
+//     launch drains for any number of workgroups; the waits are bounded
+//     anyway, and on expiry the launch records a status word and stops
+//     waiting.  Each tile needs an agent-scope acquire before it reads and a
+//     release after it writes; on a device whose XCDs have separate L2
+//     caches those invalidate and write back a whole L2, once per tile,
+//     which makes this form several times slower than round launches, whose
+//     kernel boundaries pay the same once per round.
+//
+// The launch sequence of a batch layout that repeats is captured once in a
+// hipGraph and replayed.
 //
 // Each tile runs the same tile body as a single-grid band, with the same
 // canonical per-point arithmetic, so every grid's result is bit-identical
@@ -28,14 +47,16 @@
 namespace tvs {
 namespace {
 
-constexpr int kBatchC = 4;    // nD: points per lane
-constexpr int kBatchNPT = 4;  // nD: staging values per thread (any k >= 1)
+constexpr int kBatchC = 4;    // nD points per lane of the batch's own schedules
+constexpr int kBatchNPT = 4;  // nD: staging values per thread (any k >= C/4)
+constexpr long long kBatchSpinLimit = 1ll << 22;  // ~seconds: far beyond any band
+constexpr size_t kBatchLds = 160 * 1024;          // dynamic LDS of a persistent nD launch
 
 struct BatchItem {
-    unsigned int g;
-    unsigned int b;
-    unsigned int t;
-    unsigned int pad;
+    unsigned int g;     // grid within the group
+    unsigned int b;     // band
+    unsigned int t;     // tile of the band
+    unsigned int need;  // tiles of the grid's bands before b (all done before this one)
 };
 
 template <typename T>
@@ -56,14 +77,101 @@ struct Grid1d {
     Coeffs<T> cf;
 };
 
-template <typename T, int D, bool BOX, bool PER, bool UNI>
+// Layout of a group's synchronization words in device memory.
+struct SyncWords {
+    int ticket;
+    int pad[63];   // the per-grid counters start on their own cache line
+    int done[1];   // [ngrids]
+};
+
+__global__ void batch_reset(int* sync, int ngrids) {
+    auto* s = reinterpret_cast<SyncWords*>(sync);
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0) s->ticket = 0;
+    for (int g = i; g < ngrids; g += gridDim.x * blockDim.x) s->done[g] = 0;
+}
+
+// Take the next item and wait for the bands it depends on.  Called by wave 0
+// only, every lane (no lane-dependent branch: the ticket is a scalar).
+// Returns the item index (>= nitems: no more work).
+__device__ __forceinline__ int take_item(const BatchItem* items, int nitems, SyncWords* s,
+                                         int* status) {
+    const int lane = threadIdx.x & 63;
+    const int mine = atomicAdd(&s->ticket, lane == 0 ? 1 : 0);
+    const int it = __builtin_amdgcn_readfirstlane(mine);
+    if (it < nitems) {
+        const unsigned g = items[it].g, need = items[it].need;
+        const int* done = &s->done[g];
+        long long spins = 0;
+        while ((unsigned)__hip_atomic_load(done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <
+               need) {
+            if (__hip_atomic_load(status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) != 0) break;
+            if (++spins > kBatchSpinLimit) {
+                __hip_atomic_store(status, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+                break;
+            }
+            __builtin_amdgcn_s_sleep(2);
+        }
+    }
+    return it;
+}
+
+// After a tile: its stores are made visible device-wide by every thread,
+// then one count per tile.
+__device__ __forceinline__ void finish_item(SyncWords* s, unsigned g, int wave) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __syncthreads();
+    if (wave == 0) {
+        const int lane = threadIdx.x & 63;
+        __hip_atomic_fetch_add(&s->done[g], lane == 0 ? 1 : 0, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+// Tiles of a batch form every product with its own weight (the single-grid
+// kernel's shared products for equal weights give the same bits; the batch
+// kernels skip that variant to halve their instantiations).
+// The item slot that wave 0 hands to the other waves sits in dynamic LDS at
+// byte offset slot_off, past every member's tile planes (a static __shared__
+// variable would count against the 160 KiB the tile planes may take).
+template <typename T, int D, bool BOX, bool PER, int C>
+__global__ __launch_bounds__(512) void batch_persistent_nd(const GridNd<T>* grids,
+                                                           const BatchItem* items, int nitems,
+                                                           int* sync, int* status,
+                                                           unsigned slot_off) {
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
+    int* s_item = reinterpret_cast<int*>(smem_raw + slot_off);
+    auto* s = reinterpret_cast<SyncWords*>(sync);
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    for (;;) {
+        if (wave == 0) {
+            const int it = take_item(items, nitems, s, status);
+            *s_item = it;
+        }
+        __syncthreads();
+        const int it = __builtin_amdgcn_readfirstlane(*s_item);
+        if (it >= nitems) break;
+        // the earlier bands' stores (other workgroups, other XCDs) are visible
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        const BatchItem w = items[it];
+        const GridNd<T>& gr = grids[w.g];
+        const int which = (int)w.b == gr.nbands - 1 ? 1 : 0;
+        nd::tstp_tile<T, D, BOX, PER, C, kBatchNPT, false>(
+            gr.buf[w.b & 1], gr.buf[(w.b + 1) & 1], gr.band[which], gr.cf, (int)w.t,
+            reinterpret_cast<T*>(smem_raw), threadIdx.x);
+        finish_item(s, w.g, wave);  // also orders s_item's next write after every read
+    }
+}
+
+// Round launches: block i runs item first + i of round `round`.
+template <typename T, int D, bool BOX, bool PER, bool UNI, int C>
 __global__ __launch_bounds__(512) void batch_round_nd(const GridNd<T>* grids,
                                                       const BatchItem* items, int round) {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
     const BatchItem w = items[blockIdx.x];
     const GridNd<T>& gr = grids[w.g];
     const int which = round == gr.nbands - 1 ? 1 : 0;
-    nd::tstp_tile<T, D, BOX, PER, kBatchC, kBatchNPT, UNI>(
+    nd::tstp_tile<T, D, BOX, PER, C, kBatchNPT, UNI>(
         gr.buf[round & 1], gr.buf[(round + 1) & 1], gr.band[which], gr.cf, (int)w.t,
         reinterpret_cast<T*>(smem_raw), threadIdx.x);
 }
@@ -78,6 +186,31 @@ __global__ __launch_bounds__(256) void batch_round_1d(const Grid1d<T>* grids,
                                 gr.cf, (int)w.t, threadIdx.x);
 }
 
+template <typename T, bool PER>
+__global__ __launch_bounds__(256) void batch_persistent_1d(const Grid1d<T>* grids,
+                                                           const BatchItem* items, int nitems,
+                                                           int* sync, int* status) {
+    __shared__ int s_item;
+    auto* s = reinterpret_cast<SyncWords*>(sync);
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    for (;;) {
+        if (wave == 0) {
+            const int it = take_item(items, nitems, s, status);
+            s_item = it;
+        }
+        __syncthreads();
+        const int it = __builtin_amdgcn_readfirstlane(s_item);
+        if (it >= nitems) break;
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        const BatchItem w = items[it];
+        const Grid1d<T>& gr = grids[w.g];
+        const int which = (int)w.b == gr.nbands - 1 ? 1 : 0;
+        d1::tstp1d_tile<T, PER, 64>(gr.buf[w.b & 1], gr.buf[(w.b + 1) & 1], gr.band[which],
+                                    gr.cf, (int)w.t, threadIdx.x);
+        finish_item(s, w.g, wave);
+    }
+}
+
 template <typename T>
 __global__ void copy_back(const T* __restrict__ src, T* __restrict__ dst, int64_t n) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
@@ -89,21 +222,28 @@ __global__ void copy_back(const T* __restrict__ src, T* __restrict__ dst, int64_
 // host side
 // ---------------------------------------------------------------------------
 struct Variant {
-    int dtype, ndim, shape, boundary, uniform;
+    int dtype, ndim, shape, boundary, uniform, c;
     bool operator<(const Variant& o) const {
-        return std::tie(dtype, ndim, shape, boundary, uniform) <
-               std::tie(o.dtype, o.ndim, o.shape, o.boundary, o.uniform);
+        return std::tie(dtype, ndim, shape, boundary, uniform, c) <
+               std::tie(o.dtype, o.ndim, o.shape, o.boundary, o.uniform, o.c);
     }
 };
+
+bool persistent_mode() {
+    const char* env = std::getenv("TVS_BATCH_PERSISTENT");
+    return env && env[0] == '1';
+}
 
 struct Member {
     tvs_plan* plan;
     void* grid;
     const double* coeffs;
     int64_t T;
+    Schedule sched;
 };
 
-// Schedule the batch uses for a grid: fixed lane width, depth min(k, T).
+// The batch's own schedule for a grid whose plan has no time-skewed one
+// (plain or untuned): 4 points per lane, moderate depth.
 Schedule batch_schedule(const Problem& p) {
     Schedule s;
     s.method = TVS_METHOD_TSTP;
@@ -130,6 +270,36 @@ Schedule batch_schedule(const Problem& p) {
     return s;
 }
 
+// Whether a schedule runs every band of T steps in the batch kernels: its
+// full bands and its last, shallower one (a lane group stages at most four
+// plane values per step, so few levels of many points per lane may not fit).
+bool batch_fits(const Problem& p, const Schedule& s, int64_t T) {
+    if (p.ndim > 1 && s.c != 4 && s.c != 8) return false;
+    const int kfull = (int)std::max<int64_t>(1, std::min<int64_t>(s.k, T));
+    const int64_t nbands = (T + kfull - 1) / kfull;
+    const int klast = (int)std::max<int64_t>(1, T - (nbands - 1) * kfull);
+    BandGeom gf, gl;
+    if (!band_geometry(p, s, kfull, &gf) || !band_geometry(p, s, klast, &gl)) return false;
+    // the persistent launch keeps 16 bytes of LDS past the tile planes
+    return p.ndim == 1 || std::max(gf.lds_bytes, gl.lds_bytes) + 32 <= kBatchLds;
+}
+
+// The schedule a member runs: its plan's (tuned) time-skewed schedule when
+// the batch kernels can take it, else the batch's own (4 points per lane,
+// which fits a band of any depth).  In 1D the batch pipelines are 64 lanes
+// wide.
+Schedule member_schedule(const Problem& p, const Schedule& plan_s, int64_t T) {
+    if (plan_s.method == TVS_METHOD_TSTP) {
+        Schedule s = plan_s;
+        if (p.ndim == 1) {
+            s.pl = 64;
+            s.k = std::min(64, s.k);
+        }
+        if (batch_fits(p, s, T)) return s;
+    }
+    return batch_schedule(p);
+}
+
 template <typename T>
 void fill_coeffs_t(const Problem& p, const double* c, Coeffs<T>* out) {
     for (int q = 0; q < kMaxPoints; ++q) out->c[q] = q < p.order ? (T)c[q] : T(0);
@@ -146,7 +316,7 @@ int build_group(const std::vector<Member>& ms, int ndim, std::vector<GridNd<T>>*
     std::vector<int> nb(ms.size());
     for (size_t i = 0; i < ms.size(); ++i) {
         const Problem& p = ms[i].plan->prob;
-        Schedule s = batch_schedule(p);
+        const Schedule& s = ms[i].sched;
         const int kfull = (int)std::min<int64_t>(s.k, ms[i].T);
         const int nbands = (int)((ms[i].T + kfull - 1) / kfull);
         const int klast = (int)(ms[i].T - (int64_t)(nbands - 1) * kfull);
@@ -188,33 +358,38 @@ int build_group(const std::vector<Member>& ms, int ndim, std::vector<GridNd<T>>*
         }
         if (nbands % 2) odd->push_back((int)i);
     }
-    // round b: band b of every grid that has one; items of a round are contiguous
+    // round-major order: band b of every grid that has one, then band b + 1
     int maxb = 0;
     for (int v : nb) maxb = std::max(maxb, v);
+    std::vector<unsigned> before(ms.size(), 0);  // tiles of the bands already listed
     for (int b = 0; b < maxb; ++b) {
         round_begin->push_back((int)items->size());
         for (size_t i = 0; i < ms.size(); ++i)
-            if (b < nb[i])
+            if (b < nb[i]) {
                 for (int t = 0; t < tiles_per_band[i][b]; ++t)
-                    items->push_back(BatchItem{(unsigned)i, (unsigned)b, (unsigned)t, 0u});
+                    items->push_back(BatchItem{(unsigned)i, (unsigned)b, (unsigned)t, before[i]});
+                before[i] += (unsigned)tiles_per_band[i][b];
+            }
     }
     round_begin->push_back((int)items->size());
     *lds_out = lds;
     return TVS_OK;
 }
 
-// One group, prepared on the host.  Its work list ([items | grids]) is
-// built as a host image and then uploaded either into memory the group owns
-// (synchronously, before any stream work, so that the launches can be
-// captured in a graph) or into caller-provided buffers (asynchronously).
+// One group, prepared on the host.  Its work list ([items | grids | sync
+// words]) is built as a host image and then uploaded either into memory the
+// group owns (synchronously, before any stream work, so that the launches
+// can be captured in a graph) or into caller-provided buffers
+// (asynchronously).
 struct GroupLaunch {
     Variant v;
-    void* dev = nullptr;  // [items | grids]
+    void* dev = nullptr;  // [items | grids | sync words]
     bool owned = false;   // dev was allocated for this group
     std::vector<unsigned char> image;
     size_t lds = 0;
+    int nitems = 0, ngrids = 0;
     std::vector<int> round_begin;  // item offset of each round, plus the end
-    size_t off_grids = 0;
+    size_t off_grids = 0, off_sync = 0;
     std::vector<std::pair<const void*, void*>> copies;  // odd band count: scratch -> grid
     std::vector<int64_t> copy_elems;
 };
@@ -231,10 +406,13 @@ int prepare_group(const Variant& v, const std::vector<Member>& ms, GroupLaunch* 
     if (rc) return rc;
     gl->lds = lds;
     if (items.empty()) return TVS_OK;
+    gl->nitems = (int)items.size();
+    gl->ngrids = (int)ms.size();
     gl->off_grids = (items.size() * sizeof(BatchItem) + 255) & ~(size_t)255;
     const size_t grid_bytes =
         v.ndim == 1 ? g1d.size() * sizeof(Grid1d<T>) : gnd.size() * sizeof(GridNd<T>);
-    const size_t total = gl->off_grids + grid_bytes;
+    gl->off_sync = (gl->off_grids + grid_bytes + 255) & ~(size_t)255;
+    const size_t total = gl->off_sync + sizeof(SyncWords) + ms.size() * sizeof(int);
     std::vector<unsigned char>& host = gl->image;
     host.assign(total, 0);
     std::memcpy(host.data(), items.data(), items.size() * sizeof(BatchItem));
@@ -247,9 +425,38 @@ int prepare_group(const Variant& v, const std::vector<Member>& ms, GroupLaunch* 
     return TVS_OK;
 }
 
+// Pinned status word shared by every persistent batch launch of the process:
+// 0, or 1 once a launch's bounded wait expired (results of that batch are
+// invalid).  Reported and cleared by the next stencil_batch_run.
+int* batch_status_host() {
+    static int* host = nullptr;
+    static std::once_flag once;
+    std::call_once(once, [] {
+        void* h = nullptr;
+        if (hipHostMalloc(&h, sizeof(int), hipHostMallocMapped | hipHostMallocCoherent) ==
+            hipSuccess) {
+            host = (int*)h;
+            *host = 0;
+        }
+    });
+    return host;
+}
+
+// Persistent workgroups of a kernel: as many as are resident at once on the
+// device, but no more than there are items.
+int persistent_blocks(const void* kern, int threads, size_t lds, int nitems) {
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, threads, lds) != hipSuccess ||
+        per_cu < 1)
+        per_cu = 1;
+    int dev = 0, cus = 256;
+    if (hipGetDevice(&dev) == hipSuccess)
+        (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    return std::max(1, std::min(nitems, per_cu * std::max(1, cus)));
+}
+
 template <typename T>
-int launch_group(const GroupLaunch& gl, hipStream_t st) {
-    if (!gl.dev || gl.image.empty()) return TVS_OK;
+int launch_rounds(const GroupLaunch& gl, hipStream_t st) {
     const Variant& v = gl.v;
     const int rounds = (int)gl.round_begin.size() - 1;
     for (int b = 0; b < rounds; ++b) {
@@ -269,21 +476,96 @@ int launch_group(const GroupLaunch& gl, hipStream_t st) {
             auto go = [&](auto kern) {
                 hipLaunchKernelGGL(kern, dim3(n), dim3(512), lds, st, dg, ditems, b);
             };
-#define TVS_B(DD, B, PR, U) go(batch_round_nd<T, DD, B, PR, U>)
-#define TVS_B3(DD)                                                                              \
-    if (box) {                                                                                  \
-        if (per) { if (uni) TVS_B(DD, true, true, true); else TVS_B(DD, true, true, false); }   \
-        else { if (uni) TVS_B(DD, true, false, true); else TVS_B(DD, true, false, false); }     \
-    } else {                                                                                    \
-        if (per) { if (uni) TVS_B(DD, false, true, true); else TVS_B(DD, false, true, false); } \
-        else { if (uni) TVS_B(DD, false, false, true); else TVS_B(DD, false, false, false); }   \
+#define TVS_R(DD, B, PR, U, CC) go(batch_round_nd<T, DD, B, PR, U, CC>)
+#define TVS_RC(DD, B, PR, U)                                              \
+    switch (v.c) {                                                        \
+        case 4: TVS_R(DD, B, PR, U, 4); break;                            \
+        case 8: TVS_R(DD, B, PR, U, 8); break;                            \
+        default: return set_error(TVS_E_UNSUPPORTED, "batch lane width"); \
     }
-            if (v.ndim == 2) { TVS_B3(2) } else { TVS_B3(3) }
-#undef TVS_B3
-#undef TVS_B
+#define TVS_RU(DD, B, PR)                                                 \
+    if (uni) { TVS_RC(DD, B, PR, true) } else { TVS_RC(DD, B, PR, false) }
+#define TVS_R3(DD)                                                        \
+    if (box) {                                                            \
+        if (per) { TVS_RU(DD, true, true) } else { TVS_RU(DD, true, false) }   \
+    } else {                                                              \
+        if (per) { TVS_RU(DD, false, true) } else { TVS_RU(DD, false, false) } \
+    }
+            if (v.ndim == 2) { TVS_R3(2) } else { TVS_R3(3) }
+#undef TVS_R3
+#undef TVS_RU
+#undef TVS_RC
+#undef TVS_R
         }
         TVS_HIP_TRY(hipGetLastError());
     }
+    return TVS_OK;
+}
+
+template <typename T>
+int launch_group(const GroupLaunch& gl, hipStream_t st) {
+    if (!gl.dev || gl.image.empty() || gl.nitems == 0) return TVS_OK;
+    const Variant& v = gl.v;
+    if (!persistent_mode()) {
+        int rc = launch_rounds<T>(gl, st);
+        if (rc) return rc;
+        for (size_t i = 0; i < gl.copies.size(); ++i) {
+            const int64_t n = gl.copy_elems[i];
+            hipLaunchKernelGGL(copy_back<T>, dim3((unsigned)std::min<int64_t>(4096, (n + 255) / 256)),
+                               dim3(256), 0, st, (const T*)gl.copies[i].first,
+                               (T*)gl.copies[i].second, n);
+            TVS_HIP_TRY(hipGetLastError());
+        }
+        return TVS_OK;
+    }
+    int* host_status = batch_status_host();
+    int* status = nullptr;
+    if (!host_status || hipHostGetDevicePointer((void**)&status, host_status, 0) != hipSuccess)
+        return set_error(TVS_E_DEVICE, "batch status word unavailable");
+    int* sync = (int*)((char*)gl.dev + gl.off_sync);
+    const auto* ditems = (const BatchItem*)gl.dev;
+    hipLaunchKernelGGL(batch_reset, dim3((unsigned)std::max(1, (gl.ngrids + 255) / 256)),
+                       dim3(256), 0, st, sync, gl.ngrids);
+    TVS_HIP_TRY(hipGetLastError());
+    if (v.ndim == 1) {
+        auto* dg = (const Grid1d<T>*)((char*)gl.dev + gl.off_grids);
+        auto go = [&](auto kern) {
+            const int blocks = persistent_blocks((const void*)kern, 256, 0, gl.nitems);
+            hipLaunchKernelGGL(kern, dim3(blocks), dim3(256), 0, st, dg, ditems, gl.nitems, sync,
+                               status);
+        };
+        if (v.boundary == TVS_PERIODIC) go(batch_persistent_1d<T, true>);
+        else go(batch_persistent_1d<T, false>);
+    } else {
+        auto* dg = (const GridNd<T>*)((char*)gl.dev + gl.off_grids);
+        const bool box = v.shape == TVS_BOX, per = v.boundary == TVS_PERIODIC;
+        const unsigned slot_off = (unsigned)((gl.lds + 15) & ~(size_t)15);
+        const size_t lds = slot_off + 16;
+        if (lds > kBatchLds) return set_error(TVS_E_UNSUPPORTED, "batch tile planes exceed LDS");
+        auto go = [&](auto kern) {
+            const int blocks = persistent_blocks((const void*)kern, 512, lds, gl.nitems);
+            hipLaunchKernelGGL(kern, dim3(blocks), dim3(512), lds, st, dg, ditems, gl.nitems,
+                               sync, status, slot_off);
+        };
+#define TVS_B(DD, B, PR, CC) go(batch_persistent_nd<T, DD, B, PR, CC>)
+#define TVS_BC(DD, B, PR)                                                 \
+    switch (v.c) {                                                        \
+        case 4: TVS_B(DD, B, PR, 4); break;                               \
+        case 8: TVS_B(DD, B, PR, 8); break;                               \
+        default: return set_error(TVS_E_UNSUPPORTED, "batch lane width"); \
+    }
+#define TVS_B3(DD)                                                                  \
+    if (box) {                                                                      \
+        if (per) { TVS_BC(DD, true, true) } else { TVS_BC(DD, true, false) }        \
+    } else {                                                                        \
+        if (per) { TVS_BC(DD, false, true) } else { TVS_BC(DD, false, false) }      \
+    }
+        if (v.ndim == 2) { TVS_B3(2) } else { TVS_B3(3) }
+#undef TVS_B3
+#undef TVS_BC
+#undef TVS_B
+    }
+    TVS_HIP_TRY(hipGetLastError());
     for (size_t i = 0; i < gl.copies.size(); ++i) {
         const int64_t n = gl.copy_elems[i];
         hipLaunchKernelGGL(copy_back<T>, dim3((unsigned)std::min<int64_t>(4096, (n + 255) / 256)),
@@ -295,21 +577,26 @@ int launch_group(const GroupLaunch& gl, hipStream_t st) {
 
 template <typename T>
 void set_lds_attributes() {
-    static bool done = false;
-    if (done) return;
-    done = true;
-    auto set = [](auto kern) {
-        (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  160 * 1024);
-    };
-    set(batch_round_nd<T, 2, true, true, true>);   set(batch_round_nd<T, 2, true, true, false>);
-    set(batch_round_nd<T, 2, true, false, true>);  set(batch_round_nd<T, 2, true, false, false>);
-    set(batch_round_nd<T, 2, false, true, true>);  set(batch_round_nd<T, 2, false, true, false>);
-    set(batch_round_nd<T, 2, false, false, true>); set(batch_round_nd<T, 2, false, false, false>);
-    set(batch_round_nd<T, 3, true, true, true>);   set(batch_round_nd<T, 3, true, true, false>);
-    set(batch_round_nd<T, 3, true, false, true>);  set(batch_round_nd<T, 3, true, false, false>);
-    set(batch_round_nd<T, 3, false, true, true>);  set(batch_round_nd<T, 3, false, true, false>);
-    set(batch_round_nd<T, 3, false, false, true>); set(batch_round_nd<T, 3, false, false, false>);
+    static std::once_flag once;
+    std::call_once(once, [] {
+        auto set = [](auto kern) {
+            (void)hipFuncSetAttribute((const void*)kern,
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        };
+        static_for<0, 2>([&](auto dc) {
+            constexpr int DD = decltype(dc)::value + 2;
+            static_for<0, 4>([&](auto fc) {
+                constexpr int f = decltype(fc)::value;
+                constexpr bool B = f & 1, PR = (f >> 1) & 1;
+                set(batch_persistent_nd<T, DD, B, PR, 4>);
+                set(batch_persistent_nd<T, DD, B, PR, 8>);
+                set(batch_round_nd<T, DD, B, PR, true, 4>);
+                set(batch_round_nd<T, DD, B, PR, true, 8>);
+                set(batch_round_nd<T, DD, B, PR, false, 4>);
+                set(batch_round_nd<T, DD, B, PR, false, 8>);
+            });
+        });
+    });
 }
 
 struct BatchPlan {
@@ -388,9 +675,12 @@ int prepare_batch(int n, tvs_plan* const* plans, void* const* grids, const doubl
             bp->gs.emplace_back(p, i);
             continue;
         }
-        Variant v{p->prob.dtype, p->prob.ndim, p->prob.shape, p->prob.boundary,
-                  same_weight_bits(coeffs[i], p->prob.order) ? 1 : 0};
-        groups[v].push_back(Member{p, grids[i], coeffs[i], T[i]});
+        const Schedule s = member_schedule(p->prob, p->sched, T[i]);
+        // equal weights take the shared-product tile body in round launches
+        const int uni = !persistent_mode() && same_weight_bits(coeffs[i], p->prob.order) ? 1 : 0;
+        Variant v{p->prob.dtype, p->prob.ndim, p->prob.shape, p->prob.boundary, uni,
+                  p->prob.ndim == 1 ? 0 : s.c};
+        groups[v].push_back(Member{p, grids[i], coeffs[i], T[i], s});
     }
     set_lds_attributes<double>();
     set_lds_attributes<float>();
@@ -404,7 +694,7 @@ int prepare_batch(int n, tvs_plan* const* plans, void* const* grids, const doubl
     return TVS_OK;
 }
 
-// Enqueue a prepared batch on st: the Jacobi rounds, and (with_gs) the
+// Enqueue a prepared batch on st: the Jacobi groups, and (with_gs) the
 // Gauss-Seidel members, which run through their own persistent kernel and
 // are kept out of captured graphs.  With ext->naux > 0 the Gauss-Seidel
 // members are spread over ext's auxiliary streams, after everything already
@@ -479,6 +769,7 @@ std::vector<double> layout_key(int n, tvs_plan* const* plans, void* const* grids
                                const double* const* coeffs, const int64_t* T, int device) {
     std::vector<double> key;
     key.push_back(device);
+    key.push_back(persistent_mode() ? 1 : 0);
     for (int i = 0; i < n; ++i) {
         key.push_back((double)(uintptr_t)plans[i]);
         key.push_back((double)(uintptr_t)grids[i]);
@@ -522,6 +813,9 @@ int batch_run(int n, tvs_plan* const* plans, void* const* grids, const double* c
         // the work lists must outlive the launches that read them
         if (hipStreamSynchronize(st) != hipSuccess && rc == TVS_OK)
             rc = set_error(TVS_E_DEVICE, "batch launch failed");
+        if (int* bs = batch_status_host();
+            rc == TVS_OK && bs && __atomic_exchange_n(bs, 0, __ATOMIC_ACQ_REL) != 0)
+            rc = set_error(TVS_E_DEVICE, "a batch launch timed out waiting for a band");
         free_batch(&bp);
         return rc;
     }
@@ -633,6 +927,10 @@ extern "C" int stencil_batch_run(int n, tvs_plan* const* plans, void* const* gri
             int rc = gs_report_previous(plans[i]);
             if (rc) return rc;
         }
+    // a persistent batch launch whose bounded wait expired (reported once)
+    if (int* bs = batch_status_host(); bs && __atomic_exchange_n(bs, 0, __ATOMIC_ACQ_REL) != 0)
+        return set_error(TVS_E_DEVICE, "an earlier batch launch timed out waiting for a band; "
+                                       "its results are invalid");
     const char* env = std::getenv("TVS_BATCH_GRAPH");
     const bool use_graph = !(env && env[0] == '0');
     int rc = batch_run(n, plans, grids, coeffs, T, (hipStream_t)stream, use_graph, nullptr);
