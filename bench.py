@@ -45,14 +45,14 @@ PAPER_CONTEXT = ("paper (2x 12-core Xeon E5-2670, 2.7 GHz, AVX2): scalar Gauss-S
                  "1.6x compiler auto-vectorization on Heat-1D at every core count; GS-2D 2.2x "
                  "scalar on 24 cores; LCS 5.3x scalar on 24 cores (Section 4.2)")
 METRIC = "GStencil/s + % HBM roofline vs plain sweep; p50/p99 latency mixed load"
-# workload -> (rocprof summary of its band kernel, the sources that kernel is built from)
+# workload -> (rocprof summary of its band kernel, that kernel's source and instantiation unit)
 PROFILES = {
-    "box2d9p": ("tstp_nd_box2d9p_8192_f64.md",
-                ["tstp_nd.hpp", "tstp_nd_f64_2d.hip", "jacobi_tstp.hip", "common.hpp",
-                 "kernels.hpp"]),
-    "life2d": ("tstp_nd_life2d_8000_i32.md",
-               ["tstp_nd.hpp", "tstp_nd_life_2d.hip", "jacobi_tstp.hip", "common.hpp",
-                "kernels.hpp"]),
+    "box2d9p": ("tstp_nd_box2d9p_8192_f64.md", ["tstp_nd.hpp", "tstp_nd_f64_2d.hip"]),
+    "box2d9p_f32": ("tstp_nd_box2d9p_8192_f32.md", ["tstp_nd.hpp", "tstp_nd_f32_2d.hip"]),
+    "star3d7p": ("tstp_nd_star3d7p_512_f64.md", ["tstp_nd.hpp", "tstp_nd_f64_3d.hip"]),
+    "heat1d": ("tstp1d_heat1d_100000_f64.md", ["tstp1d.hpp", "tstp1d.hip"]),
+    "star2d9p": ("tstp_ndr_star2d9p_8192_f64.md", ["tstp_ndr.hpp", "tstp_ndr_w_f64.hip"]),
+    "life2d": ("tstp_nd_life2d_8000_i32.md", ["tstp_nd.hpp", "tstp_nd_life_2d.hip"]),
 }
 
 
