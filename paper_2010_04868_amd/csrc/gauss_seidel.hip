@@ -20,9 +20,10 @@
 //     band of rows is reused by k sweeps while it is still in cache;
 //   * items are handed out by an atomic ticket in mu order to a persistent
 //     grid of waves, so every dependence points to an earlier ticket held by
-//     a running wave (no deadlock for any grid size); progress (columns
-//     completed on the item's last row) is published with agent-scope
-//     release/acquire, which also orders memory across the XCDs' L2 caches;
+//     a running wave (no deadlock for any grid size); progress (steps
+//     completed) is published to the items that depend on it, and band data
+//     crosses the XCDs' separate L2 caches through agent-scope loads and
+//     stores, so that no fence has to invalidate or write back an L2;
 //   * every wait is bounded; on expiry the kernel records a status word and
 //     the remaining waits return at once, so the launch always drains.
 // Band layout: a run first copies the interior rows into a layout of its
@@ -47,11 +48,10 @@ namespace {
 constexpr int kRows = 64;        // rows per band (one wave)
 constexpr int kBlock = 8;        // steps whose loads are issued together
 // Steps between dependency checks and progress updates (KS, a template
-// parameter chosen by row width).  Crossing the XCDs' separate L2 caches
-// makes every agent-scope acquire and release expensive (an L2 invalidate or
-// write-back), so they are done once per KS steps; a dependent item then
-// trails its producer by about KS columns.  Wide rows take 128 (fewer
-// fences), narrow ones 32 (shorter trails where little else is in flight).
+// parameter chosen by row width).  A dependent item trails its producer by
+// about KS columns, so short intervals keep more items in flight; each check
+// costs a progress load and each update a wait for the item's stores.  Wide
+// rows take 32, narrow ones 16 (measured on 256^2 to 4096^2 grids).
 constexpr long long kSpinLimit = 1ll << 22;  // ~seconds: far beyond any legitimate wait
 constexpr int kAllSteps = 1 << 30;            // progress of a finished item
 
@@ -69,6 +69,31 @@ struct GsArgs {
 
 __device__ __forceinline__ int load_relaxed(const int* p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Band data that other items read or wrote moves with agent-scope (sc1)
+// loads and stores: each is coherent across the XCDs' L2 caches by itself
+// (the same accesses a relaxed agent-scope atomic makes), so an item's waits
+// need no acquire fence (an L2 invalidate) and its progress stores no
+// release fence (an L2 write-back).  What remains of release is that the
+// item's own stores have completed before the progress store that announces
+// them (vmcnt(0)); of acquire, that its loads are issued after the progress
+// loads have returned.  The compiler barriers keep the accesses on their side.
+template <typename T>
+__device__ __forceinline__ T ld_agent(const T* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+__device__ __forceinline__ void st_agent(T* p, T v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+// s_waitcnt vmcnt(0) (expcnt and lgkmcnt left at their maximum), gfx9 encoding
+constexpr int kWaitVmcnt0 = 0x0F70;
+__device__ __forceinline__ void after_waits() { asm volatile("" ::: "memory"); }
+__device__ __forceinline__ void before_progress_store() {
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
+    asm volatile("" ::: "memory");
 }
 
 // Wait until *p >= need (or the launch has been aborted).  Uniform per wave.
@@ -164,10 +189,10 @@ __global__ __launch_bounds__(64) void gs2d(T* grid, T* lay, GsArgs a, Coeffs<T> 
         };
         // registers: west (new), centre/east (old), north and south histories
         T Wv = 0, Cv = 0, out = 0;
-        T Ev = active ? *own(0) : T(0);
+        T Ev = active ? ld_agent(own(0)) : T(0);
         T NWv, Nv, NEv, SWv, Sv, SEv;
-        NWv = Nv = NEv = active ? *above(0) : T(0);
-        SWv = Sv = SEv = active ? *below(0) : T(0);
+        NWv = Nv = NEv = active ? ld_agent(above(0)) : T(0);
+        SWv = Sv = SEv = active ? ld_agent(below(0)) : T(0);
         int* prog_self = a.progress + t * a.nb + b;
         const int* prog_north = b > 0 ? a.progress + t * a.nb + (b - 1) : nullptr;
         const int* prog_prev = t > 0 ? a.progress + (t - 1) * a.nb + b : nullptr;
@@ -200,7 +225,7 @@ __global__ __launch_bounds__(64) void gs2d(T* grid, T* lay, GsArgs a, Coeffs<T> 
               wait_at_least(prog_south, us + KS + 1 - SIG * L, a.status);
           if (prog_north) wait_at_least(prog_north, us + KS - 1 + SIG * kRows, a.status);
           // the producers' rows written before their progress stores are visible now
-          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+          after_waits();
           // An inner interval keeps every lane (idle ones included) on an
           // interior column, 0 <= c < ncols, for all of its steps: it needs no
           // test per step, and idle lanes of a partial band store into their
@@ -228,18 +253,18 @@ __global__ __launch_bounds__(64) void gs2d(T* grid, T* lay, GsArgs a, Coeffs<T> 
                   if constexpr (IN) {
                       // column strides are whole layout columns: one base per
                       // block and immediate offsets
-                      e_in[m] = own(u0 + 1 - SIG * lane)[m * kRows];
-                      se_in[m] = bptr[m * kRows];
-                      n_in[m] = nptr[m * nb_.nstride];  // lane 0's value is the one used
+                      e_in[m] = ld_agent(own(u0 + 1 - SIG * lane) + m * kRows);
+                      se_in[m] = ld_agent(bptr + m * kRows);
+                      n_in[m] = ld_agent(nptr + m * nb_.nstride);  // lane 0's is the one used
                   } else {
                       const bool ok = active && c >= -1 && ye <= n1 - 1;
                       // invalid lanes read a harmless in-band element and drop it
-                      const T e = *(ok ? own(ye) : band);
-                      const T se = *(ok ? below(ye) : band);
+                      const T e = ld_agent(ok ? own(ye) : band);
+                      const T se = ld_agent(ok ? below(ye) : band);
                       e_in[m] = ok ? e : T(0);
                       se_in[m] = ok ? se : T(0);
                       const bool okn = lane == 0 && c >= -1 && yn <= n1 - 1;
-                      const T nv = *(okn ? above(yn) : band);
+                      const T nv = ld_agent(okn ? above(yn) : band);
                       n_in[m] = okn ? nv : T(0);
                   }
               }
@@ -287,7 +312,7 @@ __global__ __launch_bounds__(64) void gs2d(T* grid, T* lay, GsArgs a, Coeffs<T> 
                               r = r + cf.c[3] * Ev;
                               r = r + cf.c[4] * Sv;
                           }
-                          if (IN || active) *own(c + 1) = r;
+                          if (IN || active) st_agent(own(c + 1), r);
                       }
                       Wv = r;
                       out = r;
@@ -313,10 +338,10 @@ __global__ __launch_bounds__(64) void gs2d(T* grid, T* lay, GsArgs a, Coeffs<T> 
           else
               interval(std::false_type{});
           // publish the steps completed
-          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+          before_progress_store();
           __hip_atomic_store(prog_self, us + KS, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        before_progress_store();
         __hip_atomic_store(prog_self, kAllSteps, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
 }
@@ -500,14 +525,12 @@ hipError_t launch_gs_t(const Problem& p, T* grid, const Coeffs<T>& cf, int sweep
     auto go = [&](auto kern) {
         hipLaunchKernelGGL(kern, dim3(waves), dim3(64), 0, st, grid, lay, a, cf);
     };
-    // sync interval by row width (measured on 600^2 and 4096^2 grids)
+    // sync interval by row width (measured on 256^2 to 4096^2 grids)
     const bool box = p.shape == TVS_BOX;
     if (a.ncols >= 2048)
-        box ? go(gs2d<T, true, 128>) : go(gs2d<T, false, 128>);
-    else if (a.ncols >= 512)
-        box ? go(gs2d<T, true, 64>) : go(gs2d<T, false, 64>);
-    else
         box ? go(gs2d<T, true, 32>) : go(gs2d<T, false, 32>);
+    else
+        box ? go(gs2d<T, true, 16>) : go(gs2d<T, false, 16>);
     return hipGetLastError();
 }
 
