@@ -407,83 +407,115 @@ __global__ __launch_bounds__(256) void gs_bottom_row(const T* grid, T* lay, int 
 // t0+g and updates x = q + 1 - 2g at its step q.  It needs the new value of
 // x-1 (its own last output) and the old values of x and x+1, which are lane
 // g-1's outputs of steps q-2 and q-1 (Section 3.2's legality rule with
-// s = 2).  Within a wave they arrive by DPP shifts; wave w's lane 0 takes
-// them from an LDS ring written by wave w-1's lane 63 (wave 0's ring holds
-// the grid itself: u[p] at slot p-3).  Wave w runs one block of 64 steps
-// behind wave w-1, so a ring slot is always written one barrier before it is
-// read; the ring keeps three blocks.  The last sweep's outputs go through
-// LDS and leave in one coalesced store per block.  Up to 16 waves: 1024
+// s = 2); within a wave they arrive by DPP shifts.  Up to 16 waves: 1024
 // sweeps in one launch, in place (writes trail reads by 2k positions).
+// One wave per workgroup, so that every wave has a SIMD to itself and a
+// step costs only its dependency chain.  Wave w's lane 0 takes its inputs, the outputs of wave w-1's lane
+// 63, from a ring in device memory, a block of kG1Block steps at a time:
+// wave w-1 stores a block's values with agent-scope stores (coherent across
+// the XCDs' L2 caches) and publishes its count of finished blocks once they
+// have completed; wave w waits for that count, loads the block with
+// agent-scope loads (lane l holds the inputs of steps 64s + l) and hands
+// them to lane 0 with readlane.  A producer also waits until its consumer
+// has finished the block whose slots it is about to overwrite (the ring
+// holds kG1Ring blocks).  Wave 0 reads the grid itself; the last sweep's
+// wave writes the grid behind every read.  Every wait is bounded: on expiry
+// the status word is set and the remaining waits return at once.
+constexpr int kG1Block = 256;  // steps per block
+constexpr int kG1Ring = 8;     // blocks per ring
+constexpr int kG1MaxWaves = 16;
+
+__global__ void gs1d_reset(int* prog, int w) {
+    if ((int)threadIdx.x < w) prog[threadIdx.x] = 0;
+}
+
 template <typename T>
-__global__ __launch_bounds__(1024) void gs1d(T* u, int n, int k, Coeffs<T> cf) {
-    constexpr int R = 3 * 64;  // ring slots: three blocks of steps
-    __shared__ T ring[16][R];
-    __shared__ T scrap[16][256];  // destinations of lanes that hand nothing on
-    __shared__ T obuf[64];
-    const int tid = threadIdx.x;
-    const int lane = tid & 63;
-    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int W = (k + 63) / 64;  // waves of the workgroup
+__device__ __forceinline__ T lane_of(T v, int l) {
+    if constexpr (sizeof(T) == 8) {
+        const long long x = __double_as_longlong(v);
+        const int lo = __builtin_amdgcn_readlane((int)(x & 0xffffffffll), l);
+        const int hi = __builtin_amdgcn_readlane((int)(x >> 32), l);
+        return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+    } else {
+        return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(64) void gs1d_mc(T* u, int n, int k, Coeffs<T> cf, T* ring,
+                                              int* prog, int* status) {
+    constexpr int BS = kG1Block, NS = BS / 64, RS = kG1Ring * BS;
+    __shared__ T rbuf[BS];        // lane 63's outputs of a block (the next wave's inputs)
+    __shared__ T obuf[BS];        // the last sweep's outputs of a block
+    __shared__ T scrap[64 + BS];  // destinations of the lanes that hand nothing on
+    const int lane = threadIdx.x;
+    const int w = blockIdx.x;
+    const int W = gridDim.x;
     const int wl = (k - 1) / 64, jl = (k - 1) % 64;  // the last sweep's lane
     const int g = 64 * w + lane;
     const T ul = u[0], ur = u[n - 1];
     const T c0 = cf.c[0], c1 = cf.c[1], c2 = cf.c[2];
-    const int b_end = ((n - 3) + 2 * (k - 1)) / 64;  // last block of the last sweep
-    const int NB = b_end + W;
+    const int b_end = ((n - 3) + 2 * (k - 1)) / BS;  // last block of the last sweep
+    const T* in_ring = ring + (size_t)w * RS;
+    T* out_ring = ring + (size_t)(w + 1) * RS;
+    T* rout = lane == 63 ? rbuf : scrap + lane;
+    T* obase = (w == wl && lane == jl) ? obuf : scrap + lane;
     T p1 = ul, p2 = ul;  // this lane's outputs of the last two steps
-    // wave 0: positions 1, 2 in slots R-2, R-1 and block 0 (positions 3..66)
-    T nxt = T(0);
-    if (w == 0) {
-        const int p = 3 + lane;
-        ring[0][lane] = p < n ? u[p] : T(0);
-        const int p2i = 1 + (lane & 1);
-        const T v2 = p2i < n ? u[p2i] : T(0);
-        ring[0][R - 2 + (lane & 1)] = v2;  // every lane writes one of the two slots
-        nxt = p + 64 < n ? u[p + 64] : T(0);
-    }
-    T* rout = (lane == 63 && w + 1 < W) ? &ring[w + 1][0] : &scrap[w][lane];
-    T* obase = (w == wl && lane == jl) ? obuf : &scrap[w][lane];
-    __syncthreads();
-    for (int B = 0; B < NB; ++B) {
-        const int b = B - w;
-        if (b >= 0 && b <= b_end) {
-            const int sb = (64 * b) % R;  // slot of step 64b
-            if (w == 0 && b > 0) {
-                ring[0][sb + lane] = nxt;  // positions 64b+3 .. 64b+66
-                const int p = 64 * (b + 1) + 3 + lane;
-                nxt = p < n ? u[p] : T(0);
-            }
-            const T* src = &ring[w][0];
-            // slots of steps 64b-2 and 64b-1
-            const int sm2 = (sb + R - 2) % R, sm1 = (sb + R - 1) % R;
-            T cin = src[sm2];
-            T ein = src[sm1];
-            static_for<0, 64>([&](auto mc) {
-                constexpr int m = decltype(mc)::value;
-                const int q = 64 * b + m;
-                // old values of x (lane g-1, step q-2) and x+1 (step q-1)
-                const T C = shift_up<64>(p2, cin);
-                T E = shift_up<64>(p1, ein);
-                const int x = q + 1 - 2 * g;
-                E = x == n - 2 ? ur : E;  // the right end is fixed
-                T f = c0 * p1;            // x-1: this sweep's new value
-                f = f + c1 * C;
-                f = f + c2 * E;
-                const bool valid = x >= 1 && x <= n - 2;
-                p2 = p1;
-                p1 = valid ? f : ul;
-                rout[sb + m] = p1;  // lane 63: the next wave's input
-                obase[m] = p1;      // the last sweep's lane: output row
-                cin = ein;
-                if constexpr (m + 1 < 64) ein = src[sb + m];  // slot of step q
-            });
-            if (w == wl) {
-                // the last sweep's outputs of this block: steps 64b + lane
-                const int x = 64 * b + lane + 1 - 2 * (k - 1);
-                const T r = obuf[lane];
-                if (x >= 1 && x <= n - 2) u[x] = r;
+    // input of step q: wave 0 the grid value at q + 3, wave w > 0 ring slot q
+    auto input = [&](int q) -> T {
+        if (w == 0) {
+            const int p = q + 3;
+            return p < n ? u[p] : T(0);
+        }
+        return ld_agent(in_ring + (q + RS) % RS);
+    };
+    for (int b = 0; b <= b_end; ++b) {
+        if (w > 0) wait_at_least(prog + w - 1, b + 1, status);
+        if (w + 1 < W && b - kG1Ring + 2 > 0) wait_at_least(prog + w + 1, b - kG1Ring + 2, status);
+        after_waits();
+        // R_j, the input of step BS*b - 2 + j: lane l holds R_{64s+l} in r[s]
+        T r[NS];
+#pragma unroll
+        for (int s2 = 0; s2 < NS; ++s2) r[s2] = input(BS * b - 2 + 64 * s2 + lane);
+        const T rlast = input(BS * b - 2 + BS);
+        static_for<0, BS>([&](auto mc) {
+            constexpr int m = decltype(mc)::value;
+            // old values of x (lane g-1, step q-2) and x+1 (step q-1)
+            const T rm = lane_of(r[m / 64], m % 64);
+            const T rm1 = m + 1 < BS ? lane_of(r[(m + 1) / 64 % NS], (m + 1) % 64) : rlast;
+            const T C = shift_up<64>(p2, rm);
+            T E = shift_up<64>(p1, rm1);
+            const int q = BS * b + m;
+            const int x = q + 1 - 2 * g;
+            E = x == n - 2 ? ur : E;  // the right end is fixed
+            T f = c0 * p1;            // x-1: this sweep's new value
+            f = f + c1 * C;
+            f = f + c2 * E;
+            // computed by every lane, then selected: no branch in the step
+            asm volatile("" : "+v"(f));
+            const bool valid = x >= 1 && x <= n - 2;
+            p2 = p1;
+            p1 = valid ? f : ul;
+            rout[m] = p1;
+            obase[m] = p1;
+        });
+        __syncthreads();
+        if (w + 1 < W) {
+#pragma unroll
+            for (int s2 = 0; s2 < NS; ++s2) {
+                const int q = BS * b + 64 * s2 + lane;
+                st_agent(out_ring + q % RS, rbuf[64 * s2 + lane]);
             }
         }
+        if (w == wl) {
+#pragma unroll
+            for (int s2 = 0; s2 < NS; ++s2) {
+                const int x = BS * b + 64 * s2 + lane + 1 - 2 * (k - 1);
+                if (x >= 1 && x <= n - 2) u[x] = obuf[64 * s2 + lane];
+            }
+        }
+        before_progress_store();
+        __hip_atomic_store(prog + w, b + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         __syncthreads();
     }
 }
@@ -564,7 +596,8 @@ hipError_t gs3d_layout(const Problem& p, void* grid, void* work, bool in, hipStr
 size_t gs_state_bytes(const Problem& p) { return p.ndim != 2 ? 256 : state_bytes(p); }
 
 size_t gs_work_bytes(const Problem& p) {
-    if (p.ndim == 1) return 256;                           // status word only
+    // status word and block counters, then one ring per wave (8-byte slots)
+    if (p.ndim == 1) return 256 + (size_t)kG1MaxWaves * kG1Ring * kG1Block * 8;
     if (p.ndim == 3) return 256 + gs3d_layout_bytes(p);  // status word, plane-major layout
     // nb bands and one slot for the bottom border row
     const size_t lay = (size_t)(bands_of(p) + 1) * (size_t)layout_width(p) * kRows * p.elem_bytes();
@@ -589,15 +622,21 @@ hipError_t launch_gs(const Problem& p, void* grid, const void* coeffs, int sweep
                      hipStream_t st) {
     if (p.ndim == 3) return launch_gs3d(p, work, coeffs, sweeps, st);
     if (p.ndim == 1) {
-        if (sweeps < 1 || sweeps > 1024 || p.dims[0] < 3) return hipErrorInvalidValue;
-        const dim3 block((unsigned)(64 * ((sweeps + 63) / 64)));
+        if (sweeps < 1 || sweeps > 64 * kG1MaxWaves || p.dims[0] < 3) return hipErrorInvalidValue;
+        const int waves = (sweeps + 63) / 64;
         const int n = (int)p.dims[0];
+        int* w = (int*)work;
+        int* prog = w + 16;
+        void* ring = (char*)work + 256;
+        hipLaunchKernelGGL(gs1d_reset, dim3(1), dim3(64), 0, st, prog, waves);
         if (p.dtype == TVS_F64)
-            hipLaunchKernelGGL((gs1d<double>), dim3(1), block, 0, st, (double*)grid, n, sweeps,
-                               *(const Coeffs<double>*)coeffs);
+            hipLaunchKernelGGL((gs1d_mc<double>), dim3((unsigned)waves), dim3(64), 0, st,
+                               (double*)grid, n, sweeps, *(const Coeffs<double>*)coeffs,
+                               (double*)ring, prog, w + 1);
         else
-            hipLaunchKernelGGL((gs1d<float>), dim3(1), block, 0, st, (float*)grid, n, sweeps,
-                               *(const Coeffs<float>*)coeffs);
+            hipLaunchKernelGGL((gs1d_mc<float>), dim3((unsigned)waves), dim3(64), 0, st,
+                               (float*)grid, n, sweeps, *(const Coeffs<float>*)coeffs,
+                               (float*)ring, prog, w + 1);
         return hipGetLastError();
     }
     if (p.dtype == TVS_F64)

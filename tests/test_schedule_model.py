@@ -369,3 +369,56 @@ def simulate_gs_items(nb, rows, ncols, sweeps, ks, sig, seed, last_rows=None):
 def test_gauss_seidel_item_waits(sig, ks, last_rows, seed):
     simulate_gs_items(nb=4, rows=5, ncols=13, sweeps=4, ks=ks, sig=sig, seed=seed,
                       last_rows=last_rows)
+
+
+def simulate_gs1d_ring(waves, blocks, bs, ring_blocks, seed, slack=0):
+    """Replay the block protocol of the multi-CU 1D Gauss-Seidel kernel with
+    random interleavings of whole blocks.  Wave w > 0 reads, at block b, the
+    inputs of steps bs*b - 2 .. bs*b + bs - 2 from its ring (slot q mod
+    ring_blocks*bs), written by wave w-1 at the block of step q; it may start
+    block b once wave w-1 has finished block b (count >= b + 1).  A wave that
+    feeds another may start block b once that wave has finished block
+    b - ring_blocks + 1 (count >= b - ring_blocks + 2; slack weakens that).  Checks that the
+    launch never stalls and that every input read is the value of its own
+    step (no slot overwritten before it was read)."""
+    import random
+    rng = random.Random(seed)
+    rs = ring_blocks * bs
+    slots = [[None] * rs for _ in range(waves)]  # ring of wave w: step whose value it holds
+    done = [0] * waves                           # finished blocks per wave
+    while min(done) < blocks:
+        ready = []
+        for w in range(waves):
+            b = done[w]
+            if b >= blocks:
+                continue
+            if w > 0 and done[w - 1] < b + 1:
+                continue
+            need = b - ring_blocks + 2 - slack
+            if w + 1 < waves and need > 0 and done[w + 1] < need:
+                continue
+            ready.append(w)
+        assert ready, f"stalled at {done}"
+        w = rng.choice(ready)
+        b = done[w]
+        if w > 0:
+            for q in range(bs * b - 2, bs * b + bs - 1):
+                if q >= 0:
+                    assert slots[w][q % rs] == q, (w, b, q, slots[w][q % rs])
+        if w + 1 < waves:
+            for q in range(bs * b, bs * b + bs):
+                slots[w + 1][q % rs] = q
+        done[w] += 1
+
+
+@pytest.mark.parametrize("ring_blocks", [2, 3, 8])
+@pytest.mark.parametrize("seed", range(4))
+def test_gauss_seidel_1d_ring(ring_blocks, seed):
+    simulate_gs1d_ring(waves=5, blocks=23, bs=4, ring_blocks=ring_blocks, seed=seed)
+
+
+def test_gauss_seidel_1d_ring_needs_its_waits():
+    # a producer allowed one block further ahead overwrites inputs not yet read
+    with pytest.raises(AssertionError, match=r"^\("):
+        for seed in range(50):
+            simulate_gs1d_ring(waves=3, blocks=30, bs=4, ring_blocks=3, seed=seed, slack=1)
