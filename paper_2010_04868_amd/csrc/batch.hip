@@ -105,7 +105,12 @@ __device__ __forceinline__ int take_item(const BatchItem* items, int nitems, Syn
         long long spins = 0;
         while ((unsigned)__hip_atomic_load(done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <
                need) {
-            if (__hip_atomic_load(status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) != 0) break;
+            // the status word lives in host memory: reading it at every poll
+            // from hundreds of waiting workgroups floods the host link and
+            // slowed whole launches several-fold, so it is read every 256 polls
+            if ((spins & 255) == 0 &&
+                __hip_atomic_load(status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) != 0)
+                break;
             if (++spins > kBatchSpinLimit) {
                 __hip_atomic_store(status, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
                 break;
