@@ -121,6 +121,19 @@ def test_gauss_seidel_1d_matches_oracle(dtype):
     assert not failures, "\n".join(failures[:20])
 
 
+def test_gauss_seidel_1d_sixteen_waves():
+    """Up to 1024 sweeps per launch run as 16 one-wave workgroups chained
+    through rings in device memory: long rows wrap every ring many times and
+    make producers wait for their consumers; T = 2100 takes three launches."""
+    coeffs = _coeffs(3, seed=61)
+    n = 30011
+    u0 = np.random.default_rng(n).random(n)
+    for T in (1000, 1024, 2100):
+        ref = oracle_sweep(u0, coeffs, STAR, 3, GAUSS_SEIDEL, DIRICHLET, T)
+        got = gpu_sweep(u0, coeffs, STAR, 3, GAUSS_SEIDEL, DIRICHLET, T, "method=tstp,k=1024")
+        assert_bitwise(got, ref, f"GS-1D n={n} T={T}")
+
+
 @pytest.mark.parametrize("shape", [STAR, BOX])
 @pytest.mark.parametrize("dtype", [F64, F32])
 def test_gauss_seidel_3d_matches_oracle(shape, dtype):
