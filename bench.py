@@ -76,6 +76,7 @@ PROFILES = {
     "heat1d": ("tstp1d_heat1d_100000_f64.md", ["tstp1d.hpp", "tstp1d.hip"]),
     "star2d9p": ("tstp_ndr_star2d9p_8192_f64.md", ["tstp_ndr.hpp", "tstp_ndr_w_f64.hip"]),
     "life2d": ("tstp_nd_life2d_8000_i32.md", ["tstp_nd.hpp", "tstp_nd_life_2d.hip"]),
+    "vc2d5p": ("tstp_ndr_vc2d5p_4096_f64.md", ["tstp_ndr.hpp", "tstp_ndr_vc2d_f64.hip"]),
 }
 
 
@@ -513,18 +514,25 @@ def varcoef_bench(torch, tvs, inputs, args, copy_gbs):
     ms = time_runs(torch, lambda: plan.run_varcoef(grid, w, p.T), args.steps)
     nu = p.updated_points()
     value = nu * p.T / (ms / 1e3) / 1e9
-    k = info["k"]
-    if p.ndim >= 2:
-        # the band depth the 2D/3D band kernel takes with 4 points per lane
-        k = min(k, 8)
+    # the schedule variable-coefficient runs take (2D: the band kernel's own
+    # tile and depth, with the weights staged in its LDS ring)
+    vtune = info["varcoef_tuning"]
+    k = int(dict(kv.split("=") for kv in vtune.split(","))["k"])
     band_ms = time_runs(torch, lambda: plan.run_varcoef(grid, w, 2 * k), 10) / 2
     ops = nu * k * (2 * p.order - 1)
     achieved = ops / (band_ms / 1e3) / 1e12
+    # a band reads the grid and the P weights of a point once and writes the
+    # point once: (2 + P) x 8 bytes per point per launch of k steps
+    alg_bytes = (2 + p.order) * 8 * nu
+    achieved_gbs = alg_bytes / (band_ms / 1e3) / 1e9
+    # k (2P - 1) operations per (2 + P) x 8 bytes: below the FP64 ridge
+    # (78.6 TFLOP/s over 8 TB/s) the band is bound by HBM
+    hbm_bound = ops / alg_bytes < 78.64e12 / (HBM_PEAK_GBS * 1e9)
     plain = tvs.Plan.for_problem(p, "method=plain")
     plain.run_varcoef(grid, w, p.T)
     plain_ms = time_runs(torch, lambda: plain.run_varcoef(grid, w, p.T), args.plain_steps)
     plain_value = nu * p.T / (plain_ms / 1e3) / 1e9
-    log(f"varcoef: {plan.tuning()} {ms:.3f} ms/solve, {value:.1f} GStencil/s; band {band_ms:.4f} ms; "
+    log(f"varcoef: {vtune} {ms:.3f} ms/solve, {value:.1f} GStencil/s; band {band_ms:.4f} ms; "
         f"plain {plain_value:.1f} GStencil/s")
     out = {
         "metric": METRIC, "value": round(value, 2), "unit": "GStencil/s", "n_gpus": 1,
@@ -539,17 +547,24 @@ def varcoef_bench(torch, tvs, inputs, args, copy_gbs):
                                 f"2D 5-point Jacobi with variable coefficients "
                                 f"{p.dims[0]}x{p.dims[1]} FP64, T={p.T}, zero Dirichlet border, "
                                 f"weights (a, a, 1-4a, a, a) per point"),
-                   "schedule": plan.tuning(), "updated_points": nu},
+                   "schedule": vtune, "updated_points": nu},
         "copy_GBs": round(copy_gbs, 1),
         "plain_sweep": {"value": round(plain_value, 2), "unit": "GStencil/s",
                         "speedup": round(value / plain_value, 3)},
-        "roofline": {"bound": "alu", "achieved": round(achieved, 3),
-                     **alu_peak(achieved, "f64"), "traffic": None,
-                     "kernel": ("tstp1d_r with LDS-staged weights" if p.ndim == 1 else
-                                "tstp_ndr with weights read per term") + " (one launch of k steps)",
-                     "kernel_ms": round(band_ms, 4),
-                     "algorithmic_bytes": (2 + p.order) * 8 * nu},
     }
+    alu = {"achieved": round(achieved, 3), **alu_peak(achieved, "f64")}
+    hbm = {"achieved": round(achieved_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": round(achieved_gbs / HBM_PEAK_GBS, 4), "algorithmic_bytes": alg_bytes}
+    kernel = ("tstp1d_r with LDS-staged weights" if p.ndim == 1 else
+              "tstp_ndr with the weights staged in its LDS ring") + " (one launch of k steps)"
+    traffic = (profiled_traffic(args.workload, vtune)
+               if args.n is None and args.T is None else None)
+    if hbm_bound:
+        out["roofline"] = {"bound": "hbm", **hbm, "traffic": traffic, "alu": alu,
+                           "kernel": kernel, "kernel_ms": round(band_ms, 4)}
+    else:
+        out["roofline"] = {"bound": "alu", **alu, "traffic": traffic, "hbm": hbm,
+                           "kernel": kernel, "kernel_ms": round(band_ms, 4)}
     if not args.no_cpu:
         t0 = time.perf_counter()
         oracle.sweep_varcoef(u0, W, p.shape, p.boundary, 50, p.order)

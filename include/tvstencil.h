@@ -103,6 +103,9 @@ typedef struct tvs_plan_info {
     int kern;          /* kernel kind: always 0 (LDS level planes) */
     char tuning[160];  /* the schedule as a tuning string that stencil_plan accepts */
     int rule;          /* TVS_RULE_WEIGHTED or TVS_RULE_LIFE */
+    char varcoef_tuning[160]; /* the schedule stencil_run_varcoef runs (2D/3D: at most
+                                 4 points per lane; without a tuning string, 2D radius 1
+                                 takes its own tile and depth) */
 } tvs_plan_info;
 
 /*

@@ -90,6 +90,7 @@ class Plan:
         out = {f: getattr(inf, f) for f, _ in inf._fields_}
         out["dims"] = tuple(inf.dims[: inf.ndim])
         out["tuning"] = inf.tuning.decode()
+        out["varcoef_tuning"] = inf.varcoef_tuning.decode()
         return out
 
     def tuning(self) -> str:

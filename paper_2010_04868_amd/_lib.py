@@ -33,7 +33,7 @@ class PlanInfo(ctypes.Structure):
         ("tile_h", ctypes.c_int), ("tile_l", ctypes.c_int), ("lane_c", ctypes.c_int),
         ("lanemap", ctypes.c_int), ("scratch_bytes", ctypes.c_size_t),
         ("pl", ctypes.c_int), ("kern", ctypes.c_int), ("tuning", ctypes.c_char * 160),
-        ("rule", ctypes.c_int),
+        ("rule", ctypes.c_int), ("varcoef_tuning", ctypes.c_char * 160),
     ]
 
 

@@ -240,7 +240,9 @@ int run_graph(tvs_plan* p, void* grid, const double* coeffs, int64_t T, hipStrea
 int make_plan(tvs_plan** out, const Problem& pr, const char* tuning) {
     int rc = TVS_OK;
     Schedule s = default_schedule(pr);
+    bool given = false;
     if (tuning && *tuning) {
+        given = true;
         bool has_method = false;
         Schedule t = s;
         rc = parse_tuning(tuning, &t, &has_method);
@@ -255,7 +257,10 @@ int make_plan(tvs_plan** out, const Problem& pr, const char* tuning) {
         s = t;
     } else {
         Schedule cached;
-        if (tune_cache_lookup(pr, &cached)) s = cached;
+        if (tune_cache_lookup(pr, &cached)) {
+            s = cached;
+            given = true;
+        }
     }
     rc = check_schedule(pr, s);
     if (rc) return rc;
@@ -263,6 +268,7 @@ int make_plan(tvs_plan** out, const Problem& pr, const char* tuning) {
     if (!p) return set_error(TVS_E_NOMEM, "out of host memory");
     p->prob = pr;
     p->sched = s;
+    p->sched_given = given;
     *out = p;
     return TVS_OK;
 }
@@ -316,6 +322,8 @@ int stencil_plan_info(const tvs_plan* p, tvs_plan_info* info) {
     info->kern = p->sched.kern;
     info->rule = p->prob.rule;
     std::snprintf(info->tuning, sizeof info->tuning, "%s", format_tuning(p->prob, p->sched).c_str());
+    std::snprintf(info->varcoef_tuning, sizeof info->varcoef_tuning, "%s",
+                  format_tuning(p->prob, varcoef_schedule(p->prob, p->sched, p->sched_given)).c_str());
     return TVS_OK;
 }
 
@@ -431,19 +439,13 @@ int stencil_run_varcoef(tvs_plan* p, void* grid, const void* weights, int64_t T,
     int cur = 0;
     // Time-skewed schedules run bands of k levels: in 1D the 64-lane
     // pipelines with the weights staged in LDS, in 2D and 3D the band kernel
-    // with the weights read per term.  Plain schedules, and bands the
-    // schedule's tile shape cannot take, run plain steps.
+    // (2D radius 1: the weights staged in its LDS ring; else read per term).
+    // Plain schedules, and bands the schedule's tile shape cannot take, run
+    // plain steps.
     const bool band = p->sched.method == TVS_METHOD_TSTP;
-    int k = pr.ndim == 1 ? std::max(1, std::min(64, p->sched.k)) : std::max(1, p->sched.k);
-    // 2D/3D: the plan's tile shape with 4 points per lane (the band kernel
-    // with weights per term takes no more), as deep as the tile allows
-    Schedule vs = p->sched;
-    if (pr.ndim >= 2 && band) {
-        if (vs.c > 4) vs.c = 4;
-        BandGeom probe;
-        while (k > 1 && !ndr_geometry(pr, vs, k, &probe, true)) --k;
-    }
-    const int Lv = p->sched.l > 0 ? p->sched.l : 256;
+    const Schedule vs = varcoef_schedule(pr, p->sched, p->sched_given);
+    const int k = pr.ndim == 1 ? std::max(1, std::min(64, vs.k)) : std::max(1, vs.k);
+    const int Lv = vs.l > 0 ? vs.l : 256;
     CoeffBuf none;
     std::memset(none.bytes, 0, sizeof none.bytes);
     int64_t done = 0;

@@ -20,6 +20,7 @@ struct RunGraph {
 struct tvs_plan {
     tvs::Problem prob;
     tvs::Schedule sched;
+    bool sched_given = false;  // the schedule came from a tuning string or the tuning cache
     void* scratch = nullptr;  // Jacobi second buffer
     size_t scratch_bytes = 0;
     void* gs_work = nullptr;  // Gauss-Seidel ticket, status word, progress counters

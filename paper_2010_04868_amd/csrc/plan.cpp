@@ -25,8 +25,8 @@ int set_error(int code, const std::string& msg) {
 void clear_error() { g_last_error.clear(); }
 const char* last_error() { return g_last_error.c_str(); }
 
-// Radius from the point count (Section 1: "orders (number of neighbors,
-// 3-point, 5-point, ...)"): star P = 2*d*r + 1, box P = (2r+1)^d.
+// Radius from the point count, which Section 1 uses as a stencil's order:
+// star P = 2*d*r + 1, box P = (2r+1)^d.
 static int radius_of(int ndim, int shape, int order) {
     for (int r = 1; r <= 8; ++r) {
         int P = 1;
@@ -179,8 +179,9 @@ double band_cost(const Problem& p, const BandGeom& g) {
 }
 
 // Choose the stream-segment length for a geometry: the one with the least
-// modelled time over all points, with full-machine rounds.
-void choose_segment(const Problem& p, Schedule* s) {
+// modelled time over all points, with full-machine rounds.  vc: the band
+// kernel of variable coefficients (its LDS weight ring counted).
+void choose_segment(const Problem& p, Schedule* s, bool vc) {
     if (p.ndim == 1) return;
     const int nstream = (int)p.dims[0];
     double best = 1e300;
@@ -189,7 +190,7 @@ void choose_segment(const Problem& p, Schedule* s) {
         Schedule t = *s;
         t.l = l;
         BandGeom g;
-        if (!band_geometry(p, t, t.k, &g)) continue;
+        if (vc ? !ndr_geometry(p, t, t.k, &g, true) : !band_geometry(p, t, t.k, &g)) continue;
         double c = band_cost(p, g);
         if (c < best - 1e-9) {
             best = c;
@@ -304,6 +305,32 @@ Schedule default_schedule(const Problem& p) {
 }
 
 // Is a schedule runnable for this problem (all bands it will need)?
+// Schedule of variable-coefficient runs.  1D takes the plan's schedule.  2D
+// and 3D run the band kernel with at most 4 points per lane; given: the
+// plan's schedule came from a tuning string or the tuning cache (its tile
+// and depth are kept), else a 2D radius-1 plan takes the geometry measured
+// best with the LDS weight ring (4096^2 FP64 5-point: 8 levels on 128-wide
+// tiles, 227 GStencil/s against 217 for 5 levels on 256 and 206 for 6 on
+// 96).  The depth is lowered until the band fits the LDS.
+Schedule varcoef_schedule(const Problem& p, const Schedule& s, bool given) {
+    if (p.ndim == 1 || s.method != TVS_METHOD_TSTP) return s;
+    Schedule v = s;
+    v.c = std::min(v.c, 4);
+    if (!given && p.ndim == 2 && p.radius == 1) {
+        v.c = 4;
+        v.k = 8;
+        v.w = 128;
+        v.lanemap = 1;
+        // narrow grids: shrink the tile so that it is not mostly halo
+        while (v.w > 32 && v.w - 2 * v.k > 2 * p.dims[1]) v.w /= 2;
+        if (v.w <= 2 * v.k) v.k = std::max(1, v.w / 4);
+        choose_segment(p, &v, true);
+    }
+    BandGeom g;
+    while (v.k > 1 && !ndr_geometry(p, v, v.k, &g, true)) --v.k;
+    return v;
+}
+
 int check_schedule(const Problem& p, const Schedule& s) {
     if (s.method == TVS_METHOD_PLAIN) return TVS_OK;
     if (s.k < 1) return set_error(TVS_E_INVALID, "k must be >= 1");

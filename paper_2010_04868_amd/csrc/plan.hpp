@@ -15,7 +15,8 @@ int parse_tuning(const char* str, Schedule* s, bool* has_method);
 std::string format_tuning(const Problem& p, const Schedule& s);
 Schedule default_schedule(const Problem& p);
 int check_schedule(const Problem& p, const Schedule& s);
-void choose_segment(const Problem& p, Schedule* s);
+void choose_segment(const Problem& p, Schedule* s, bool vc = false);
+Schedule varcoef_schedule(const Problem& p, const Schedule& s, bool given);
 int wgs_per_cu(const BandGeom& g);
 double band_cost(const Problem& p, const BandGeom& g);
 

@@ -42,7 +42,7 @@ bool ndr_geometry(const Problem& p, const Schedule& s, int k, BandGeom* out, boo
     g.ntx = ((int)p.dims[p.ndim - 1] + g.Wv - 1) / g.Wv;
     g.nty = p.ndim == 3 ? ((int)p.dims[1] + g.Hv - 1) / g.Hv : 1;
     g.nseg = ((int)p.dims[0] + g.Lv - 1) / g.Lv;
-    g.lds_bytes = ndr::ndr_lds_bytes(p, g);
+    g.lds_bytes = ndr::ndr_lds_bytes(p, g, vc);
     if (g.lds_bytes > 160 * 1024) return false;
     *out = g;
     return true;

@@ -26,11 +26,17 @@
 //     centre value the lane read R steps earlier (a ring of R raw rows).
 //
 // Variable coefficients (VC): the weight of offset q at point e is
-// wts[q * N + e] (N grid points), read from memory by the lane that forms the
-// term -- every level reads the same weights, so they stay in cache across
-// the band.  Products are never shared between terms: every term is its own
-// weight times its value, in canonical order, so the result is bit-identical
-// to the naive sweep.
+// wts[q * N + e] (N grid points).  Every level needs the same weights, each
+// at a different step.  A 2D radius-1 band with one staged element per
+// thread stages them in an LDS ring: at step q the workgroup stores the P
+// weights of point row q+1 of its tile (loaded two steps earlier with
+// coalesced row loads), and a level reads the weights of the point rows it
+// updates from the ring, which holds the 2Rk + 2 rows in flight (level j at
+// step q updates rows q - 2Rj .. q + 2R - 2Rj).  So each weight crosses HBM
+// once per band instead of once per level.  Elsewhere (3D: a plane of
+// weights per row) the lane that forms a term loads its weight.  Products are never shared between terms: every term is its own weight
+// times its value, in canonical order, so the result is bit-identical to
+// the naive sweep.
 #pragma once
 
 #include <algorithm>
@@ -51,6 +57,13 @@ struct Unroll {
     static_assert(U % (2 * R) == 0 && U % DP == 0, "compile-time ring indices");
 };
 
+// Whether a band stages its variable coefficients in an LDS ring: 2D radius
+// 1 with one staged element per thread (a thread then loads at most P <= 9
+// weights of a row; at radius 2 the weights in flight spill registers).
+constexpr bool ndr_weight_ring(bool vc, int D, int R, int npt) {
+    return vc && D == 2 && R == 1 && npt == 1;
+}
+
 template <typename T, int D, bool BOX, int R, bool PER, int C, int NPT, bool VC>
 __global__ __launch_bounds__(512) void tstp_ndr(const T* __restrict__ in, T* __restrict__ out,
                                                 ArgsNd a, Coeffs<T> cf,
@@ -68,6 +81,11 @@ __global__ __launch_bounds__(512) void tstp_ndr(const T* __restrict__ in, T* __r
     constexpr int SL = R + 1;                   // LDS slots per level
     constexpr int DP = Unroll<R>::DP;
     constexpr int U = Unroll<R>::U;
+    // weights staged in an LDS ring; a thread loads at most P weights per step
+    constexpr bool WR = ndr_weight_ring(VC, D, R, NPT);
+    constexpr int DPW = 2;                     // weight rows are loaded DPW steps ahead
+    static_assert(U % DPW == 0, "compile-time weight prefetch slot");
+    constexpr int NWL = WR ? P : 1;
 
     const int tid = threadIdx.x;
     const int k = a.k;
@@ -105,7 +123,12 @@ __global__ __launch_bounds__(512) void tstp_ndr(const T* __restrict__ in, T* __r
 
     // LDS plane of level l (0..k) in slot r (0..R)
     auto plane = [&](int l, int r) -> T* { return lds + (r * (k + 1) + l) * a.PSP; };
-    for (int e = tid; e < (k + 1) * SL * a.PSP; e += a.NT) lds[e] = T(0);
+    // WR: weight ring after the planes, NSW slots of P rows (transposed
+    // layout, row stride Wp); slot of point row r is r mod NSW
+    const int NSW = 2 * R * k + 2;
+    T* const wring = lds + (k + 1) * SL * a.PSP;
+    const int n_lds = (k + 1) * SL * a.PSP + (WR ? NSW * P * Wp : 0);
+    for (int e = tid; e < n_lds; e += a.NT) lds[e] = T(0);
 
     // staging of level 0 (loads) and level k (stores), as in the radius-1 kernel
     const int PS = a.H * a.W;
@@ -162,6 +185,39 @@ __global__ __launch_bounds__(512) void tstp_ndr(const T* __restrict__ in, T* __r
         if (D == 3) wy = PER ? (int)wrap_idx(gy_lane, a.ny) : (int)clamp_idx(gy_lane, a.ny);
     }
     const int64_t npts = (int64_t)a.nz * a.ny * a.nx;
+    // WR: this thread's share of a weight row (P terms x W columns): element
+    // e = tid + i*NT is term e / W at tile column e % W
+    const int nwl = WR ? (P * a.W + a.NT - 1) / a.NT : 0;
+    int wl_lds[NWL];
+    int64_t wl_off[NWL];
+    T prew[DPW][NWL];
+    if constexpr (WR) {
+#pragma unroll
+        for (int i = 0; i < NWL; ++i) {
+            const int e = tid + i * a.NT;
+            wl_lds[i] = -1;
+            wl_off[i] = 0;
+            if (i < nwl && e < P * a.W) {
+                const int q2 = e / a.W, xl = e - q2 * a.W;
+                const int ox = x_org + xl;
+                const int gxx = PER ? (int)wrap_idx(ox, a.nx) : (int)clamp_idx(ox, a.nx);
+                wl_lds[i] = q2 * Wp + (xl % C) * S + xl / C + 1;
+                wl_off[i] = (int64_t)q2 * npts + gxx;
+            }
+#pragma unroll
+            for (int d = 0; d < DPW; ++d) prew[d][i] = T(0);
+        }
+    }
+    // WR: load the weights of point row r (tile-local) into dst
+    auto issue_wload = [&](int r, T* dst) {
+        int zr = z_org + r;
+        zr = PER ? (int)wrap_idx(zr, a.nz) : (int)clamp_idx(zr, a.nz);
+        const int64_t row = (int64_t)zr * a.nx;
+#pragma unroll
+        for (int i = 0; i < NWL; ++i)
+            if (wl_lds[i] >= 0) dst[i] = wts[wl_off[i] + row];
+    };
+    auto wslot_of = [&](int r) { return ((r % NSW) + NSW) % NSW; };
 
     T Acc[NA][C];
     T prevc[R][C];
@@ -208,7 +264,15 @@ __global__ __launch_bounds__(512) void tstp_ndr(const T* __restrict__ in, T* __r
         // level j reads row p of level j-1 (emitted R steps ago) and emits
         // row p - R
         const int p = q + R - 2 * R * j;
-        if constexpr (VC) {
+        if constexpr (WR) {
+            // point row q + 1 enters the weight ring (loaded DPW steps ago);
+            // row q + 1 + DPW is requested
+            T* wr = wring + wslot_of(q + 1) * P * Wp;
+#pragma unroll
+            for (int i = 0; i < NWL; ++i)
+                if (wl_lds[i] >= 0) wr[wl_lds[i]] = prew[d % DPW][i];
+            issue_wload(q + 1 + DPW, prew[d % DPW]);
+        } else if constexpr (VC) {
             // the weight addresses are formed afresh each step: hoisted out
             // of the loop, the P x C loop-invariant parts would each hold a
             // 64-bit register pair for the whole band
@@ -221,7 +285,10 @@ __global__ __launch_bounds__(512) void tstp_ndr(const T* __restrict__ in, T* __r
             // is that term's (its row is p - off(q2, 0))
             auto weight = [&](auto qc, int c) -> T {
                 constexpr int q2 = decltype(qc)::value;
-                if constexpr (VC) {
+                if constexpr (WR) {
+                    const T* wr = wring + wslot_of(p - St::off(q2, 0)) * P * Wp;
+                    return wr[q2 * Wp + c * S + gx + 1];
+                } else if constexpr (VC) {
                     int zr = z_org + p - St::off(q2, 0);
                     zr = PER ? (int)wrap_idx(zr, a.nz) : (int)clamp_idx(zr, a.nz);
                     const int64_t at = (int64_t)q2 * npts +
@@ -270,7 +337,7 @@ __global__ __launch_bounds__(512) void tstp_ndr(const T* __restrict__ in, T* __r
                     // VC: keep each point's weight loads next to their use
                     // (hoisted over the whole step they would hold P x C
                     // registers)
-                    if constexpr (VC) __builtin_amdgcn_sched_barrier(0);
+                    if constexpr (VC && !WR) __builtin_amdgcn_sched_barrier(0);
                     static_for<-R, R + 1>([&](auto dc2) {
                         constexpr int dd = decltype(dc2)::value;
                         T acc = dd == R ? f[c] : dd == -R ? s[c] : Acc[slot(dd)][c];
@@ -311,6 +378,11 @@ __global__ __launch_bounds__(512) void tstp_ndr(const T* __restrict__ in, T* __r
     lds_barrier();  // LDS zeroed
 #pragma unroll
     for (int d = 0; d < DP; ++d) issue_load(d, pre[d]);
+    if constexpr (WR) {
+        // step d stores point row d + 1
+#pragma unroll
+        for (int d = 0; d < DPW; ++d) issue_wload(d + 1, prew[d]);
+    }
     // level k emits its last row (Lin - 1 - kR) at step Lin - 1 - kR + 2Rk;
     // it is stored one step later
     const int Q = a.Lin + R * k + 1;
@@ -345,9 +417,15 @@ inline LayoutR layout_r(int D, int R, int C, int W, int H) {
     return l;
 }
 
-inline size_t ndr_lds_bytes(const Problem& p, const BandGeom& g) {
+// vc: variable coefficients; a band with the weight ring adds 2Rk + 2 slots
+// of P rows
+inline size_t ndr_lds_bytes(const Problem& p, const BandGeom& g, bool vc = false) {
     const LayoutR l = layout_r(p.ndim, p.radius, g.C, g.W, g.H);
-    return (size_t)(g.k + 1) * (p.radius + 1) * l.PSP * p.elem_bytes();
+    size_t n = (size_t)(g.k + 1) * (p.radius + 1) * l.PSP;
+    const int npt = (g.H * g.W + g.NT - 1) / g.NT;
+    if (ndr_weight_ring(vc, p.ndim, p.radius, npt))
+        n += (size_t)(2 * p.radius * g.k + 2) * p.order * l.Wp;
+    return n * p.elem_bytes();
 }
 
 inline ArgsNd make_args_r(const Problem& p, const BandGeom& g) {
@@ -405,7 +483,7 @@ template <typename T, int D, bool BOX, int R, bool VC>
 hipError_t launch_ndr_impl(const Problem& p, const BandGeom& g, const T* in, T* out,
                            const Coeffs<T>& cf, const T* wts, hipStream_t st) {
     const ArgsNd a = make_args_r(p, g);
-    const size_t lds = ndr_lds_bytes(p, g);
+    const size_t lds = ndr_lds_bytes(p, g, VC);
     const int npt = (a.H * a.W + a.NT - 1) / a.NT;
     const bool per = p.boundary == TVS_PERIODIC;
     dim3 grid((unsigned)g.blocks()), block((unsigned)g.NT);

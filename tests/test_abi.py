@@ -85,6 +85,26 @@ def test_plan_info_reports_schedule():
         == E["TVS_E_INVALID"]
 
 
+def test_varcoef_schedule():
+    """Variable-coefficient runs take at most 4 points per lane; a 2D
+    radius-1 plan without a tuning string takes the weight-ring geometry (8
+    levels on 128-wide tiles), a tuning string keeps its tile and depth, and
+    the reported schedule re-creates itself."""
+    def vc(plan):
+        return dict(kv.split("=") for kv in plan.info()["varcoef_tuning"].split(","))
+    d = vc(tvs.Plan((4096, 4096), F64, STAR, 5))
+    assert (d["method"], d["k"], d["w"], d["c"]) == ("tstp", "8", "128", "4")
+    e = vc(tvs.Plan((4096, 4096), F64, STAR, 5, tuning="method=tstp,k=3,w=64,c=8"))
+    assert (e["k"], e["w"], e["c"]) == ("3", "64", "4")
+    assert vc(tvs.Plan((4096, 4096), F64, STAR, 5, tuning="method=plain"))["method"] == "plain"
+    # narrow grids shrink the tile; 1D keeps the plan's pipeline
+    n = vc(tvs.Plan((4096, 40), F64, BOX, 9))
+    assert int(n["w"]) <= 64 and int(n["w"]) > 2 * int(n["k"])
+    assert vc(tvs.Plan((100000,), F64, STAR, 3))["k"] == str(tvs.Plan((100000,), F64, STAR, 3).info()["k"])
+    t = tvs.Plan((4096, 4096), F64, STAR, 5).info()["varcoef_tuning"]
+    assert tvs.Plan((4096, 4096), F64, STAR, 5, tuning=t).info()["varcoef_tuning"] == t
+
+
 @pytest.mark.parametrize("dims,shape,order,dep", [
     ((8192, 8192), BOX, 9, 0), ((512, 512, 512), STAR, 7, 0), ((100000,), STAR, 3, 0),
     ((4096, 4096), STAR, 5, 1), ((100, 100), STAR, 5, 0)])

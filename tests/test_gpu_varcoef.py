@@ -2,9 +2,9 @@
 per point, fixed over time): bit-exact against the oracle's variable-
 coefficient sweep (FP64, and FP32 against its FP32 mirror).  1D runs the
 time-skewed pipeline at several depths and segment lengths; 2D and 3D run
-the band kernel with the weights read per term (radius 1 and 2; 3D radius 3
-runs plain steps).  Weights are distinct per point and offset, so an offset
-or point mix-up shows."""
+the band kernel (radius 1 and 2; 3D radius 3 runs plain steps), in 2D both
+with the weights read per term and staged in the LDS ring.  Weights are
+distinct per point and offset, so an offset or point mix-up shows."""
 import numpy as np
 import pytest
 
@@ -21,7 +21,12 @@ CASES = [((97,), STAR, 3), ((1000,), STAR, 3), ((4099,), STAR, 3), ((300,), STAR
          ((80, 150), STAR, 9), ((70, 140), BOX, 25), ((60, 130), STAR, 13),
          ((20, 40, 44), STAR, 7), ((18, 36, 40), BOX, 27), ((24, 40, 44), STAR, 13),
          ((12, 14, 16), STAR, 19)]
-BAND_TUNINGS = {2: ["method=tstp,k=2,w=32,c=4,l=16", "method=tstp,k=3,w=64,c=4,l=20,lanemap=0"],
+# 2D: k = 2 and 3 read each weight per term; k = 5 and 6 (one staged element
+# per thread) stage the weights of radius-1 stencils in the LDS ring, with
+# ragged row shares (P x W not a multiple of the thread count: 9 x 40 over
+# 50 threads, 5 x 64 over 96)
+BAND_TUNINGS = {2: ["method=tstp,k=2,w=32,c=4,l=16", "method=tstp,k=3,w=64,c=4,l=20,lanemap=0",
+                    "method=tstp,k=5,w=40,c=4,l=16", "method=tstp,k=6,w=64,c=4,l=24,lanemap=1"],
                 3: ["method=tstp,k=1,w=16,h=16,c=4,l=8",
                     "method=tstp,k=2,w=32,h=16,c=4,l=12,lanemap=1"]}
 
