@@ -56,7 +56,7 @@ extern "C" {
 #define TVS_E_INVALID (-1)     /* null pointer, bad enum, T < 0, bad tuning */
 #define TVS_E_SHAPE (-2)       /* ndim not 1..3, an extent < 2r+1, size overflow */
 #define TVS_E_ORDER (-3)       /* point count inconsistent with ndim and shape */
-#define TVS_E_UNSUPPORTED (-4) /* e.g. periodic Gauss-Seidel, a 3D box of radius > 1 */
+#define TVS_E_UNSUPPORTED (-4) /* e.g. periodic Gauss-Seidel, the 3D radius-3 box */
 #define TVS_E_NOMEM (-5)       /* device or host allocation failed */
 #define TVS_E_DEVICE (-6)      /* a HIP call failed or a kernel reported abort */
 #define TVS_E_BUSY (-7)        /* server: budget or queue full */
@@ -115,9 +115,10 @@ typedef struct tvs_plan_info {
  *   dtype       TVS_F32 or TVS_F64 (storage and arithmetic precision)
  *   shape       TVS_STAR or TVS_BOX
  *   order       number of stencil points P (star: 2*ndim*r+1, box: (2r+1)^ndim);
- *               stars of radius 1..3 and boxes of at most 27 points (every
- *               radius-1 box, the 1D boxes up to radius 3, the 2D radius-2
- *               box); Gauss-Seidel: radius 1 only
+ *               stars and boxes of radius 1..3 with at most 125 points
+ *               (every one but the 3D radius-3 box, 343 points); boxes of
+ *               more than 27 points (2D radius 3, 3D radius 2) run plain
+ *               steps; Gauss-Seidel: radius 1 only
  *   dependence  TVS_JACOBI or TVS_GAUSS_SEIDEL
  *   boundary    TVS_DIRICHLET or TVS_PERIODIC (Gauss-Seidel: Dirichlet only)
  *   tuning      NULL: the tuned default (autotune cache, else a model-based
@@ -204,10 +205,13 @@ int stencil_plan_check(tvs_plan *plan);
  *            only, not retained
  * Jacobi plans only (Gauss-Seidel: TVS_E_UNSUPPORTED; Life: TVS_E_INVALID).
  * Plans with a time-skewed schedule run bands of k levels: 1D with the
- * weights staged in LDS (up to 64 levels), 2D and 3D (radius 1 and 2) on the
- * plan's tile shape with 4 points per lane, each weight read by the level
- * that forms its term; 3D radius 3 and plain schedules run one step per
- * launch.
+ * weights staged in LDS (up to 64 levels), 2D and 3D (radius 1 and 2, at
+ * most 27 points) with 4 points per lane: 2D radius 1 with each point row's
+ * weights staged in an LDS ring and, without a tuning string, its own tile
+ * and depth (stencil_plan_info's varcoef_tuning), the others on the plan's
+ * tile shape with each weight read by the level that forms its term.  3D
+ * radius 3, boxes of more than 27 points and plain schedules run one step
+ * per launch.
  */
 int stencil_run_varcoef(tvs_plan *plan, void *grid, const void *weights, int64_t T, void *stream);
 

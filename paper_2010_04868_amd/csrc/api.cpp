@@ -17,8 +17,8 @@ using namespace tvs;
 namespace tvs {
 
 template <typename T>
-static Coeffs<T> make_coeffs(const double* c, int P) {
-    Coeffs<T> k{};
+static Coeffs<T, kMaxWeights> make_coeffs(const double* c, int P) {
+    Coeffs<T, kMaxWeights> k{};
     for (int q = 0; q < P; ++q) k.c[q] = (T)c[q];  // FP32: round to nearest even
     return k;
 }
@@ -346,7 +346,7 @@ int stencil_plan_destroy(tvs_plan* p) {
 int stencil_run(tvs_plan* p, void* grid, const double* coeffs, int64_t T, void* stream) {
     clear_error();
     if (!p || !grid) return set_error(TVS_E_INVALID, "NULL argument");
-    static const double kNoWeights[kMaxPoints] = {};
+    static const double kNoWeights[kMaxWeights] = {};
     if (p->prob.rule == TVS_RULE_LIFE) coeffs = kNoWeights;  // the rule has no weights
     if (!coeffs) return set_error(TVS_E_INVALID, "NULL argument");
     if (T < 0) return set_error(TVS_E_INVALID, "T < 0");

@@ -37,7 +37,7 @@ namespace tvs {
 
 // Coefficients in the plan's precision, laid out as the kernels take them.
 struct CoeffBuf {
-    alignas(16) unsigned char bytes[sizeof(Coeffs<double>)];
+    alignas(16) unsigned char bytes[sizeof(Coeffs<double, kMaxWeights>)];
 };
 
 void fill_coeffs(const Problem& p, const double* c, CoeffBuf* out);

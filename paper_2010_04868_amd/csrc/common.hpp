@@ -22,7 +22,8 @@ namespace tvs {
 // Problem description (host side).
 // ---------------------------------------------------------------------------
 constexpr int kMaxDim = 3;
-constexpr int kMaxPoints = 27;  // radius-1 box in 3D
+constexpr int kMaxPoints = 27;    // weights a band kernel takes (the radius-1 box in 3D)
+constexpr int kMaxWeights = 125;  // weights of any stencil (the radius-2 box in 3D)
 
 struct Problem {
     int ndim = 0;
@@ -74,9 +75,11 @@ void clear_error();
 // ---------------------------------------------------------------------------
 // Coefficients as a kernel argument (canonical order, storage precision).
 // ---------------------------------------------------------------------------
-template <typename T>
+// N: capacity (the plain steps of stencils of more than kMaxPoints points
+// take exactly their own count).
+template <typename T, int N = kMaxPoints>
 struct Coeffs {
-    T c[kMaxPoints];
+    T c[N];
 };
 
 // ---------------------------------------------------------------------------

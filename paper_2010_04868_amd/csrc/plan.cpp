@@ -74,8 +74,8 @@ int validate(Problem* pr, int ndim, const int64_t* dims, int dtype, int shape, i
         return set_error(TVS_E_UNSUPPORTED, "radius " + std::to_string(r) + " " +
                                                 (shape == TVS_BOX ? "box" : "star") + " in " +
                                                 std::to_string(ndim) +
-                                                "D: radius 2 and 3 stars, the 1D radius 3 and the "
-                                                "2D radius 2 box (at most 27 weights) are implemented");
+                                                "D: every star and box of radius 2 and 3 but the "
+                                                "3D radius-3 box (343 weights) is implemented");
     if (dependence == TVS_GAUSS_SEIDEL && boundary == TVS_PERIODIC)
         return set_error(TVS_E_UNSUPPORTED, "Gauss-Seidel with a periodic boundary");
     if (dependence == TVS_GAUSS_SEIDEL && ndim == 3 && dims[0] - 2 > 65535)

@@ -15,6 +15,7 @@
 // one lane per step.  Segments of L outputs overlap by k*R input points per
 // side (a trapezoid in time), so pipelines never wait for each other.
 #include <algorithm>
+#include <cstring>
 
 #include "kernels.hpp"
 
@@ -25,13 +26,20 @@ __device__ __forceinline__ int64_t wrap64(int64_t i, int64_t n) {
     return i < 0 ? i + n : (i >= n ? i - n : i);
 }
 
+// Weights a plain step takes: at least kMaxPoints, else the stencil's count.
+template <int D, bool BOX, int R>
+constexpr int plain_cap() {
+    return StencilR<D, BOX, R>::P > kMaxPoints ? StencilR<D, BOX, R>::P : kMaxPoints;
+}
+
 // VC: variable coefficients, the weight of offset q at point e is wts[q * N + e]
 template <typename T, int D, bool BOX, int R, bool PER, bool VC = false>
 __global__ __launch_bounds__(256) void plain_r(const T* __restrict__ in, T* __restrict__ out,
-                                               int64_t n0, int64_t n1, int64_t n2, Coeffs<T> cf,
+                                               int64_t n0, int64_t n1, int64_t n2,
+                                               Coeffs<T, plain_cap<D, BOX, R>()> cf,
                                                const T* __restrict__ wts = nullptr) {
     using S = StencilR<D, BOX, R>;
-    static_assert(S::P <= kMaxPoints, "weights");
+    static_assert(S::P <= kMaxWeights, "weights");
     const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
     const int64_t ext[3] = {n0, n1, n2};
     int64_t total = 1;
@@ -147,11 +155,14 @@ __global__ __launch_bounds__(256) void tstp1d_r(const T* __restrict__ in, T* __r
         for (int i = lane; i < Lv && X0 + i < n; i += 64) out[X0 + i] = obuf[i];
 }
 
+// coeffs: the plan's coefficient buffer (kMaxWeights entries of T)
 template <typename T, int D, bool BOX, int R>
-hipError_t plain_r_go(const Problem& p, const T* in, T* out, const Coeffs<T>& cf,
+hipError_t plain_r_go(const Problem& p, const T* in, T* out, const void* coeffs,
                       hipStream_t st) {
     const int64_t total = p.elems();
     const dim3 grid((unsigned)((total + 255) / 256));
+    Coeffs<T, plain_cap<D, BOX, R>()> cf;
+    std::memcpy(&cf, coeffs, sizeof cf);
     if (p.boundary == TVS_PERIODIC)
         hipLaunchKernelGGL((plain_r<T, D, BOX, R, true>), grid, dim3(256), 0, st, in, out,
                            p.dims[0], p.dims[1], p.dims[2], cf);
@@ -162,7 +173,7 @@ hipError_t plain_r_go(const Problem& p, const T* in, T* out, const Coeffs<T>& cf
 }
 
 template <typename T>
-hipError_t plain_radius_t(const Problem& p, const T* in, T* out, const Coeffs<T>& cf,
+hipError_t plain_radius_t(const Problem& p, const T* in, T* out, const void* cf,
                           hipStream_t st) {
     const bool box = p.shape == TVS_BOX;
     const int r = p.radius;
@@ -172,9 +183,11 @@ hipError_t plain_radius_t(const Problem& p, const T* in, T* out, const Coeffs<T>
     } else if (p.ndim == 2) {
         if (r == 2) return box ? plain_r_go<T, 2, true, 2>(p, in, out, cf, st)
                                : plain_r_go<T, 2, false, 2>(p, in, out, cf, st);
-        if (r == 3 && !box) return plain_r_go<T, 2, false, 3>(p, in, out, cf, st);
+        if (r == 3) return box ? plain_r_go<T, 2, true, 3>(p, in, out, cf, st)
+                               : plain_r_go<T, 2, false, 3>(p, in, out, cf, st);
     } else {
-        if (r == 2 && !box) return plain_r_go<T, 3, false, 2>(p, in, out, cf, st);
+        if (r == 2) return box ? plain_r_go<T, 3, true, 2>(p, in, out, cf, st)
+                               : plain_r_go<T, 3, false, 2>(p, in, out, cf, st);
         if (r == 3 && !box) return plain_r_go<T, 3, false, 3>(p, in, out, cf, st);
     }
     return hipErrorInvalidValue;
@@ -225,7 +238,7 @@ template <typename T, int D, bool BOX, int R>
 hipError_t plain_vc_go(const Problem& p, const T* in, T* out, const T* wts, hipStream_t st) {
     const int64_t total = p.elems();
     const dim3 grid((unsigned)((total + 255) / 256));
-    const Coeffs<T> none{};
+    const Coeffs<T, plain_cap<D, BOX, R>()> none{};
     if (p.boundary == TVS_PERIODIC)
         hipLaunchKernelGGL((plain_r<T, D, BOX, R, true, true>), grid, dim3(256), 0, st, in, out,
                            p.dims[0], p.dims[1], p.dims[2], none, wts);
@@ -248,11 +261,13 @@ hipError_t plain_vc_t(const Problem& p, const T* in, T* out, const T* wts, hipSt
                                : plain_vc_go<T, 2, false, 1>(p, in, out, wts, st);
         if (r == 2) return box ? plain_vc_go<T, 2, true, 2>(p, in, out, wts, st)
                                : plain_vc_go<T, 2, false, 2>(p, in, out, wts, st);
-        if (r == 3 && !box) return plain_vc_go<T, 2, false, 3>(p, in, out, wts, st);
+        if (r == 3) return box ? plain_vc_go<T, 2, true, 3>(p, in, out, wts, st)
+                               : plain_vc_go<T, 2, false, 3>(p, in, out, wts, st);
     } else {
         if (r == 1) return box ? plain_vc_go<T, 3, true, 1>(p, in, out, wts, st)
                                : plain_vc_go<T, 3, false, 1>(p, in, out, wts, st);
-        if (r == 2 && !box) return plain_vc_go<T, 3, false, 2>(p, in, out, wts, st);
+        if (r == 2) return box ? plain_vc_go<T, 3, true, 2>(p, in, out, wts, st)
+                               : plain_vc_go<T, 3, false, 2>(p, in, out, wts, st);
         if (r == 3 && !box) return plain_vc_go<T, 3, false, 3>(p, in, out, wts, st);
     }
     return hipErrorInvalidValue;
@@ -323,13 +338,12 @@ hipError_t launch_tstp1d_varcoef(const Problem& p, int k, int Lv, const void* in
     return tstp1d_vc_t<float>(p, k, Lv, (const float*)in, (float*)out, (const float*)wts, st);
 }
 
-// Which (ndim, shape, radius > 1) combinations have kernels: weights of at
-// most kMaxPoints points.
+// Which (ndim, shape, radius > 1) combinations have kernels: every star and
+// box of radius 2 and 3 with at most kMaxWeights points (all but the 3D
+// radius-3 box, 343 points).
 bool radius_supported(int ndim, int shape, int r) {
     if (r < 2 || r > 3) return false;
-    if (ndim == 1) return true;
-    if (ndim == 2) return shape == TVS_STAR || r == 2;
-    return shape == TVS_STAR;
+    return !(ndim == 3 && shape == TVS_BOX && r == 3);
 }
 
 // LDS bytes of a 1D radius-R band (four pipelines per workgroup).
@@ -340,10 +354,8 @@ size_t tstp1d_radius_lds_bytes(const Problem& p, int k, int Lv) {
 hipError_t launch_plain_radius(const Problem& p, const void* in, void* out, const void* coeffs,
                                hipStream_t st) {
     if (p.dtype == TVS_F64)
-        return plain_radius_t<double>(p, (const double*)in, (double*)out,
-                                      *(const Coeffs<double>*)coeffs, st);
-    return plain_radius_t<float>(p, (const float*)in, (float*)out, *(const Coeffs<float>*)coeffs,
-                                 st);
+        return plain_radius_t<double>(p, (const double*)in, (double*)out, coeffs, st);
+    return plain_radius_t<float>(p, (const float*)in, (float*)out, coeffs, st);
 }
 
 hipError_t launch_tstp1d_radius(const Problem& p, const BandGeom& g, const void* in, void* out,

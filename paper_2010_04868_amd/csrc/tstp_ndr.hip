@@ -13,6 +13,8 @@ bool ndr_geometry(const Problem& p, const Schedule& s, int k, BandGeom* out, boo
     // values and 6 running sums per point exceed the registers of a lane);
     // boxes of radius 2 and above only in 2D
     if (p.ndim == 3 && (R == 3 || (R == 2 && p.shape == TVS_BOX))) return false;
+    // the 2D radius-3 box (49 weights) runs plain steps
+    if (p.order > kMaxPoints) return false;
     // 8 points per lane only for 2D constant weights
     if (s.c == 8 && (vc || p.ndim == 3)) return false;
     const int64_t plane_bytes =

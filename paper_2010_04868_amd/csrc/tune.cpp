@@ -185,7 +185,7 @@ extern "C" int stencil_tune(tvs_plan* p, void* grid, const double* coeffs, int64
                             void* stream, char* best, size_t best_len) {
     clear_error();
     if (!p || !grid) return set_error(TVS_E_INVALID, "NULL argument");
-    static const double kNoWeights[kMaxPoints] = {};
+    static const double kNoWeights[kMaxWeights] = {};
     if (p->prob.rule == TVS_RULE_LIFE) coeffs = kNoWeights;  // the rule has no weights
     if (!coeffs) return set_error(TVS_E_INVALID, "NULL argument");
     if (T_probe < 1) return set_error(TVS_E_INVALID, "T_probe must be >= 1");

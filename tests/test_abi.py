@@ -51,8 +51,8 @@ def code_of(fn):
     (((8, 8), F64, STAR, 5, 4, DIRICHLET), "TVS_E_INVALID"),
     (((8, 8), F64, STAR, 5, JACOBI, 5), "TVS_E_INVALID"),
     (((8, 8), F64, STAR, 5, GAUSS_SEIDEL, PERIODIC), "TVS_E_UNSUPPORTED"),
-    (((9, 9, 9), F64, BOX, 125, JACOBI, DIRICHLET), "TVS_E_UNSUPPORTED"),  # 125 weights
-    (((9, 9), F64, BOX, 49, JACOBI, DIRICHLET), "TVS_E_UNSUPPORTED"),      # radius 3 box
+    (((9, 9, 9), F64, BOX, 343, JACOBI, DIRICHLET), "TVS_E_UNSUPPORTED"),  # 3D radius-3 box
+    (((9, 9), F64, BOX, 49, GAUSS_SEIDEL, DIRICHLET), "TVS_E_UNSUPPORTED"),  # radius 3 GS
     (((20,), F64, STAR, 9, JACOBI, DIRICHLET), "TVS_E_UNSUPPORTED"),       # radius 4
     (((20,), F64, STAR, 5, GAUSS_SEIDEL, DIRICHLET), "TVS_E_UNSUPPORTED"),  # radius 2 GS
     (((70000, 3, 3), F64, STAR, 7, GAUSS_SEIDEL, DIRICHLET), "TVS_E_UNSUPPORTED"),
@@ -155,6 +155,13 @@ def test_radius_plans_without_device():
     assert (t["k"], t["s"], t["tile_w"], t["lane_c"], t["tile_l"]) == (3, 6, 64, 4, 20)
     r3 = tvs.Plan((9, 9, 9), F32, STAR, 19).info()                  # 3D radius 3: plain steps
     assert r3["radius"] == 3 and r3["method"] == 0
+    # boxes of more than 27 points (2D radius 3, 3D radius 2): plain steps,
+    # and no band schedule is accepted for them
+    for dims, P, r in (((500, 600), 49, 3), ((50, 60, 70), 125, 2)):
+        big = tvs.Plan(dims, F64, BOX, P).info()
+        assert big["radius"] == r and big["method"] == 0 and big["order"] == P
+    assert code_of(lambda: tvs.Plan((500, 600), F64, BOX, 49, tuning="method=tstp,k=2,w=64,c=4")) \
+        == E["TVS_E_INVALID"]
     for bad in ("method=tstp,k=4,w=64,c=4,s=3",                      # the skew is 2r
                 "method=tstp,k=8,w=32,c=4",                          # 2kr halo columns >= w
                 "method=tstp,k=2,w=64,c=16"):                        # 4 or 8 points per lane

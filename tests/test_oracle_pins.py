@@ -161,6 +161,8 @@ BRUTE_CASES = [
     ((6, 7), BOX, 2, 2),
     ((5, 5, 6), STAR, 2, 2),
     ((17,), STAR, 3, 3),
+    ((8, 9), BOX, 3, 2),
+    ((6, 6, 7), BOX, 2, 1),
 ]
 
 
@@ -716,7 +718,8 @@ def varcoef_bruteforce(u0, shape, r, W, boundary, T):
 
 @pytest.mark.parametrize("dims,shape,r,T", [((12,), STAR, 1, 4), ((13,), STAR, 2, 3),
                                             ((5, 6), STAR, 1, 3), ((5, 6), BOX, 1, 2),
-                                            ((4, 4, 5), STAR, 1, 2)])
+                                            ((4, 4, 5), STAR, 1, 2), ((8, 9), BOX, 3, 1),
+                                            ((6, 6, 7), BOX, 2, 1)])
 @pytest.mark.parametrize("boundary", [DIRICHLET, PERIODIC])
 def test_varcoef_exact_bruteforce(dims, shape, r, T, boundary):
     P = len(offset_list(len(dims), shape, r))
