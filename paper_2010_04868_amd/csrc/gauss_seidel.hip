@@ -40,6 +40,7 @@
 // order, after all of its "new" and before any of its "old" neighbours are
 // overwritten, so the result is bit-identical to the naive lexicographic
 // sweep.
+#include "gs_order.hpp"
 #include "kernels.hpp"
 
 namespace tvs {
@@ -87,6 +88,18 @@ template <typename T>
 __device__ __forceinline__ void st_agent(T* p, T v) {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
+// The value `lane` holds (the same in every lane).
+template <typename T>
+__device__ __forceinline__ T read_lane(T v, int lane) {
+    if constexpr (sizeof(T) == 8) {
+        const uint64_t u = __builtin_bit_cast(uint64_t, v);
+        const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)u, lane);
+        const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), lane);
+        return __builtin_bit_cast(T, ((uint64_t)hi << 32) | lo);
+    } else {
+        return __builtin_bit_cast(T, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), lane));
+    }
+}
 // s_waitcnt vmcnt(0) (expcnt and lgkmcnt left at their maximum), gfx9 encoding
 constexpr int kWaitVmcnt0 = 0x0F70;
 __device__ __forceinline__ void after_waits() { asm volatile("" ::: "memory"); }
@@ -116,22 +129,6 @@ __global__ void gs_reset(int* ticket, int* progress, int n) {
     for (; i < n; i += gridDim.x * blockDim.x) progress[i] = 0;
 }
 
-// item -> (band, sweep) in mu = 2*sweep + band order
-__device__ void decode_item(int item, int nb, int sweeps, int* b, int* t) {
-    int rem = item;
-    for (int mu = 0;; ++mu) {
-        int t_lo = mu - (nb - 1) > 0 ? (mu - (nb - 1) + 1) / 2 : 0;
-        int t_hi = min(sweeps - 1, mu / 2);
-        int cnt = t_hi >= t_lo ? t_hi - t_lo + 1 : 0;
-        if (rem < cnt) {
-            *t = t_lo + rem;
-            *b = mu - 2 * *t;
-            return;
-        }
-        rem -= cnt;
-    }
-}
-
 // Column y of the row above / below the band, in whichever array holds it.
 template <typename T>
 struct GsRows {
@@ -144,7 +141,7 @@ struct GsRows {
 template <typename T, bool BOX, int KS>
 __global__ __launch_bounds__(64) void gs2d(T* grid, T* lay, GsArgs a, Coeffs<T> cf) {
     constexpr int SIG = BOX ? 2 : 1;
-    static_assert(KS % kBlock == 0, "sync interval");
+    static_assert(KS % kBlock == 0 && kBlock % 2 == 0, "sync interval; even block starts");
     const int lane = threadIdx.x;
     const int n1 = a.n1;
     const int64_t Wp = a.Wp;
@@ -159,7 +156,7 @@ __global__ __launch_bounds__(64) void gs2d(T* grid, T* lay, GsArgs a, Coeffs<T> 
         const int item = __builtin_amdgcn_readfirstlane(mine);
         if (item >= a.nitems) break;
         int b, t;
-        decode_item(item, a.nb, a.sweeps, &b, &t);
+        gs::decode_item(item, a.nb, a.sweeps, &b, &t);
         const int x0 = 1 + kRows * b;
         const int rows = min(kRows, a.n0 - 1 - x0);
         const int L = rows - 1;  // last row of the band
@@ -187,8 +184,13 @@ __global__ __launch_bounds__(64) void gs2d(T* grid, T* lay, GsArgs a, Coeffs<T> 
             return lane > 0 ? band + (int64_t)(y + SIG * (lane - 1)) * kRows + lane - 1
                             : nb_.north + (int64_t)y * nb_.nstride;
         };
-        // registers: west (new), centre/east (old), north and south histories
+        // registers: west (new), centre/east (old), north and south histories;
+        // seh: the south-east values of the last SIG steps (step u in slot
+        // u mod SIG: intervals and blocks start at even steps)
         T Wv = 0, Cv = 0, out = 0;
+        T seh[SIG];
+#pragma unroll
+        for (int i = 0; i < SIG; ++i) seh[i] = T(0);
         T Ev = active ? ld_agent(own(0)) : T(0);
         T NWv, Nv, NEv, SWv, Sv, SEv;
         NWv = Nv = NEv = active ? ld_agent(above(0)) : T(0);
@@ -238,63 +240,45 @@ __global__ __launch_bounds__(64) void gs2d(T* grid, T* lay, GsArgs a, Coeffs<T> 
             // values the waits above cover, and old values no lane overwrites
             // before the block's steps, so they may be issued a block early.
             auto load_blk = [&](int u0, T (&e_in)[kBlock], T (&se_in)[kBlock], T (&n_in)[kBlock]) {
-              // row below at column u0+1-SIG*lane, and lane 0's row above at
-              // column u0-1+SIG (the same address in every lane)
-              const T* bptr = lane < L ? band + (int64_t)(u0 + 1 + SIG) * kRows + lane + 1
-                                       : nb_.south + (int64_t)(u0 + 1 - SIG * lane) * kRows;
-              const T* nptr = nb_.north + (int64_t)(u0 - 1 + SIG) * nb_.nstride;
-              (void)bptr;
-              (void)nptr;
 #pragma unroll
               for (int m = 0; m < kBlock; ++m) {
                   const int c = u0 + m - 1 - SIG * lane;
                   const int ye = c + 2;
                   const int yn = c + SIG;
-                  if constexpr (IN) {
-                      // column strides are whole layout columns: one base per
-                      // block and immediate offsets
-                      e_in[m] = ld_agent(own(u0 + 1 - SIG * lane) + m * kRows);
-                      se_in[m] = ld_agent(bptr + m * kRows);
-                      n_in[m] = ld_agent(nptr + m * nb_.nstride);  // lane 0's is the one used
-                  } else {
-                      const bool ok = active && c >= -1 && ye <= n1 - 1;
-                      // invalid lanes read a harmless in-band element and drop it
-                      const T e = ld_agent(ok ? own(ye) : band);
-                      const T se = ld_agent(ok ? below(ye) : band);
-                      e_in[m] = ok ? e : T(0);
-                      se_in[m] = ok ? se : T(0);
-                      const bool okn = lane == 0 && c >= -1 && yn <= n1 - 1;
-                      const T nv = ld_agent(okn ? above(yn) : band);
-                      n_in[m] = okn ? nv : T(0);
-                  }
+                  const bool ok = active && c >= -1 && ye <= n1 - 1;
+                  // invalid lanes read a harmless in-band element and drop it
+                  const T e = ld_agent(ok ? own(ye) : band);
+                  const T se = ld_agent(ok ? below(ye) : band);
+                  e_in[m] = ok ? e : T(0);
+                  se_in[m] = ok ? se : T(0);
+                  const bool okn = lane == 0 && c >= -1 && yn <= n1 - 1;
+                  const T nv = ld_agent(okn ? above(yn) : band);
+                  n_in[m] = okn ? nv : T(0);
               }
             };
-            auto comp_blk = [&](int u0, const T (&e_in)[kBlock], const T (&se_in)[kBlock],
-                                const T (&n_in)[kBlock]) {
-#pragma unroll
-              for (int m = 0; m < kBlock; ++m) {
-                  // value of the row above, one column ahead of where the row
-                  // above was last step: lane i-1's last output; for lane 0 the
-                  // north row
-                  const T nin = shift_up<64>(out, n_in[m]);
-                  const int c = u0 + m - 1 - SIG * lane;
-                  if (IN || (c >= -1 && c <= a.ncols)) {
+            // Step u: nin is the value of the row above one column ahead of
+            // where it was last step (lane i-1's last output; for lane 0 the
+            // north row), ein the east value, sein the south-east one.
+            auto step = [&](int u, T nin, T ein, T sein, auto inner_s) {
+                  constexpr bool IS = decltype(inner_s)::value;
+                  const int c = u - 1 - SIG * lane;
+                  if (IS || (c >= -1 && c <= a.ncols)) {
                       if (BOX) {
                           NWv = Nv;
                           Nv = NEv;
                           NEv = nin;
                           SWv = Sv;
                           Sv = SEv;
-                          SEv = se_in[m];
+                          SEv = sein;
                       } else {
                           Nv = nin;
                           Sv = SEv;
-                          SEv = se_in[m];
+                          SEv = sein;
                       }
                       Cv = Ev;
-                      Ev = e_in[m];
+                      Ev = ein;
                       T r = Cv;  // border columns pass their fixed value along
-                      if (IN || (c >= 0 && c < a.ncols)) {
+                      if (IS || (c >= 0 && c < a.ncols)) {
                           if (BOX) {
                               r = cf.c[0] * NWv;
                               r = r + cf.c[1] * Nv;
@@ -312,16 +296,56 @@ __global__ __launch_bounds__(64) void gs2d(T* grid, T* lay, GsArgs a, Coeffs<T> 
                               r = r + cf.c[3] * Ev;
                               r = r + cf.c[4] * Sv;
                           }
-                          if (IN || active) st_agent(own(c + 1), r);
+                          if (IS || active) st_agent(own(c + 1), r);
                       }
                       Wv = r;
                       out = r;
                   }
+            };
+            // Steps of a block outside inner intervals: every lane loads its
+            // own east value.  seh keeps the south-east values of the last
+            // SIG steps for the inner interval that may follow.
+            auto comp_blk = [&](int u0, const T (&e_in)[kBlock], const T (&se_in)[kBlock],
+                                const T (&n_in)[kBlock]) {
+#pragma unroll
+              for (int m = 0; m < kBlock; ++m) {
+                  const T nin = shift_up<64>(out, n_in[m]);
+                  seh[m % SIG] = se_in[m];
+                  step(u0 + m, nin, e_in[m], se_in[m], std::false_type{});
               }
             };
+            if constexpr (IN) {
+              // An inner interval issues every load of its KS steps at once,
+              // right after its waits: the south-east values of each step,
+              // and lane 0's east and north values with one load each
+              // (lane j holds step us + j's), read back with readlane.
+              // (lane 0's values first: the counter of outstanding loads
+              // drains in issue order)
+              T e_vec = T(0), n_vec = T(0);
+              if (lane < KS) {
+                  e_vec = ld_agent(band + (int64_t)(us + 1 + lane) * kRows);
+                  n_vec = ld_agent(nb_.north + (int64_t)(us - 1 + SIG + lane) * nb_.nstride);
+              }
+              // the row below at column us+1-SIG*lane onwards (lane L: the
+              // south row); column strides are whole layout columns
+              T se_all[KS];
+              const T* bptr = lane < L ? band + (int64_t)(us + 1 + SIG) * kRows + lane + 1
+                                       : nb_.south + (int64_t)(us + 1 - SIG * lane) * kRows;
+#pragma unroll
+              for (int m = 0; m < KS; ++m) se_all[m] = ld_agent(bptr + m * kRows);
+#pragma unroll
+              for (int m = 0; m < KS; ++m) {
+                  const T n0 = read_lane(n_vec, m), e0 = read_lane(e_vec, m);
+                  const T nin = shift_up<64>(out, n0);
+                  const T ein = shift_up<64>(seh[m % SIG], e0);
+                  seh[m % SIG] = se_all[m];
+                  step(us + m, nin, ein, se_all[m], std::true_type{});
+              }
+              return;
+            }
             // blocks of the interval (the last interval stops at U), the next
             // block's loads in flight while a block computes
-            const int uend = IN ? us + KS : min(us + KS, U);
+            const int uend = min(us + KS, U);
             T eA[kBlock], seA[kBlock], nA[kBlock], eB[kBlock], seB[kBlock], nB[kBlock];
             load_blk(us, eA, seA, nA);
             for (int u0 = us; u0 < uend; u0 += 2 * kBlock) {

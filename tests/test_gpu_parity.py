@@ -102,6 +102,28 @@ def test_gauss_seidel_wide_rows(shape, dtype):
     assert not failures, "\n".join(failures[:20])
 
 
+@pytest.mark.parametrize("shape", [STAR, BOX])
+@pytest.mark.parametrize("dtype", [F64, F32])
+def test_gauss_seidel_many_bands(shape, dtype):
+    # 17 and 18 bands of 64 rows, the last of 1, 10 and 64 rows, rows narrow
+    # and wide enough for 32-step intervals (inner intervals take a lane's
+    # east value from its neighbour's south-east value of SIG steps before)
+    P = npoints(2, shape)
+    coeffs = _coeffs(P, seed=60 + shape)
+    failures = []
+    for dims in [(1027, 300), (1100, 700), (1090, 2100)]:
+        u0 = np.random.default_rng(sum(dims)).random(dims).astype(np_dtype(dtype))
+        for T in (1, 3, 8):
+            ref = oracle_sweep(u0, coeffs, shape, P, GAUSS_SEIDEL, DIRICHLET, T)
+            for tuning in ("method=tstp,k=2", "method=tstp,k=5", None):
+                got = gpu_sweep(u0, coeffs, shape, P, GAUSS_SEIDEL, DIRICHLET, T, tuning)
+                try:
+                    assert_bitwise(got, ref, f"GS dims={dims} T={T} tuning={tuning}")
+                except AssertionError as e:
+                    failures.append(str(e))
+    assert not failures, "\n".join(failures[:20])
+
+
 @pytest.mark.parametrize("dtype", [F64, F32])
 def test_gauss_seidel_1d_matches_oracle(dtype):
     # lanes are sweeps: 1, 3, 64 (one wave), 65 and 200 (chained waves) per launch
