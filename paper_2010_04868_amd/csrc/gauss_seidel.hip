@@ -51,8 +51,9 @@ constexpr int kBlock = 8;        // steps whose loads are issued together
 // Steps between dependency checks and progress updates (KS, a template
 // parameter chosen by row width).  A dependent item trails its producer by
 // about KS columns, so short intervals keep more items in flight; each check
-// costs a progress load and each update a wait for the item's stores.  Wide
-// rows take 32, narrow ones 16 (measured on 256^2 to 4096^2 grids).
+// costs a progress load and each update a wait for the item's stores.  Rows
+// of 2048 columns or more take 16, narrower ones 8 (measured on 600^2 to
+// 4096^2 grids once the polls no longer contend, see gs_reset).
 constexpr long long kSpinLimit = 1ll << 22;  // ~seconds: far beyond any legitimate wait
 constexpr int kAllSteps = 1 << 30;            // progress of a finished item
 
@@ -65,7 +66,7 @@ struct GsArgs {
     int Wp;       // layout columns per band row
     int* ticket;
     int* status;
-    int* progress;  // [sweeps][nb]
+    int* progress;  // [sweeps][nb], one counter per kProgStride ints
 };
 
 __device__ __forceinline__ int load_relaxed(const int* p) {
@@ -111,10 +112,14 @@ __device__ __forceinline__ void before_progress_store() {
 
 // Wait until *p >= need (or the launch has been aborted).  Uniform per wave.
 // Relaxed polling: the caller issues one acquire fence after all its waits.
+// The status word, one line read by every waiting wave of the launch, is
+// read every 64 polls only.
 __device__ __forceinline__ void wait_at_least(const int* p, int need, int* status) {
     long long spins = 0;
     while (load_relaxed(p) < need) {
-        if (__hip_atomic_load(status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return;
+        if ((spins & 63) == 63 &&
+            __hip_atomic_load(status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0)
+            return;
         if (++spins > kSpinLimit) {
             __hip_atomic_store(status, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             return;
@@ -123,10 +128,16 @@ __device__ __forceinline__ void wait_at_least(const int* p, int need, int* statu
     }
 }
 
+// The 2D kernel's progress counters sit one per cache line: the waves that
+// poll a counter and the item that publishes it then share that line with
+// no other counter's traffic (packed 32 to a line, their agent-scope polls
+// and stores all queued on the same lines).
+constexpr int kProgStride = 32;  // ints: 128 bytes
+
 __global__ void gs_reset(int* ticket, int* progress, int n) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i == 0) *ticket = 0;
-    for (; i < n; i += gridDim.x * blockDim.x) progress[i] = 0;
+    for (; i < n; i += gridDim.x * blockDim.x) progress[(int64_t)i * kProgStride] = 0;
 }
 
 // Column y of the row above / below the band, in whichever array holds it.
@@ -195,11 +206,11 @@ __global__ __launch_bounds__(64) void gs2d(T* grid, T* lay, GsArgs a, Coeffs<T> 
         T NWv, Nv, NEv, SWv, Sv, SEv;
         NWv = Nv = NEv = active ? ld_agent(above(0)) : T(0);
         SWv = Sv = SEv = active ? ld_agent(below(0)) : T(0);
-        int* prog_self = a.progress + t * a.nb + b;
-        const int* prog_north = b > 0 ? a.progress + t * a.nb + (b - 1) : nullptr;
-        const int* prog_prev = t > 0 ? a.progress + (t - 1) * a.nb + b : nullptr;
-        const int* prog_south =
-            (t > 0 && b + 1 < a.nb) ? a.progress + (t - 1) * a.nb + (b + 1) : nullptr;
+        auto counter = [&](int tt, int bb) { return a.progress + (int64_t)(tt * a.nb + bb) * kProgStride; };
+        int* prog_self = counter(t, b);
+        const int* prog_north = b > 0 ? counter(t, b - 1) : nullptr;
+        const int* prog_prev = t > 0 ? counter(t - 1, b) : nullptr;
+        const int* prog_south = (t > 0 && b + 1 < a.nb) ? counter(t - 1, b + 1) : nullptr;
 
         // steps: at step u, lane i updates column u - SIG*i (c = u - 1 - SIG*i
         // in [-1, ncols]).  Progress is published as the number of steps an
@@ -553,7 +564,8 @@ int64_t layout_width(const Problem& p) {
     return p.dims[1] + (int64_t)(kRows - 1) * (p.shape == TVS_BOX ? 2 : 1);
 }
 size_t state_bytes(const Problem& p) {
-    const size_t raw = (size_t)(64 + (size_t)bands_of(p) * kMaxSweeps + 64) * sizeof(int);
+    const size_t raw =
+        (size_t)(64 + (size_t)bands_of(p) * kMaxSweeps * kProgStride + 64) * sizeof(int);
     return (raw + 255) / 256 * 256;
 }
 
@@ -581,12 +593,12 @@ hipError_t launch_gs_t(const Problem& p, T* grid, const Coeffs<T>& cf, int sweep
     auto go = [&](auto kern) {
         hipLaunchKernelGGL(kern, dim3(waves), dim3(64), 0, st, grid, lay, a, cf);
     };
-    // sync interval by row width (measured on 256^2 to 4096^2 grids)
+    // sync interval by row width (measured on 600^2 to 4096^2 grids)
     const bool box = p.shape == TVS_BOX;
     if (a.ncols >= 2048)
-        box ? go(gs2d<T, true, 32>) : go(gs2d<T, false, 32>);
-    else
         box ? go(gs2d<T, true, 16>) : go(gs2d<T, false, 16>);
+    else
+        box ? go(gs2d<T, true, 8>) : go(gs2d<T, false, 8>);
     return hipGetLastError();
 }
 
