@@ -78,17 +78,21 @@ struct Grid1d {
 };
 
 // Layout of a group's synchronization words in device memory.
+// Per-grid counters of finished tiles, one per cache line: the workgroups
+// that poll a grid's counter and the tiles that bump it then share that line
+// with no other grid's traffic.
+constexpr int kDoneStride = 32;  // ints: 128 bytes
 struct SyncWords {
     int ticket;
     int pad[63];   // the per-grid counters start on their own cache line
-    int done[1];   // [ngrids]
+    int done[1];   // [ngrids * kDoneStride], grid g's counter at done[g * kDoneStride]
 };
 
 __global__ void batch_reset(int* sync, int ngrids) {
     auto* s = reinterpret_cast<SyncWords*>(sync);
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i == 0) s->ticket = 0;
-    for (int g = i; g < ngrids; g += gridDim.x * blockDim.x) s->done[g] = 0;
+    for (int g = i; g < ngrids; g += gridDim.x * blockDim.x) s->done[g * kDoneStride] = 0;
 }
 
 // Take the next item and wait for the bands it depends on.  Called by wave 0
@@ -101,7 +105,7 @@ __device__ __forceinline__ int take_item(const BatchItem* items, int nitems, Syn
     const int it = __builtin_amdgcn_readfirstlane(mine);
     if (it < nitems) {
         const unsigned g = items[it].g, need = items[it].need;
-        const int* done = &s->done[g];
+        const int* done = &s->done[g * kDoneStride];
         long long spins = 0;
         while ((unsigned)__hip_atomic_load(done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <
                need) {
@@ -128,7 +132,7 @@ __device__ __forceinline__ void finish_item(SyncWords* s, unsigned g, int wave) 
     __syncthreads();
     if (wave == 0) {
         const int lane = threadIdx.x & 63;
-        __hip_atomic_fetch_add(&s->done[g], lane == 0 ? 1 : 0, __ATOMIC_RELAXED,
+        __hip_atomic_fetch_add(&s->done[g * kDoneStride], lane == 0 ? 1 : 0, __ATOMIC_RELAXED,
                                __HIP_MEMORY_SCOPE_AGENT);
     }
 }
@@ -417,7 +421,7 @@ int prepare_group(const Variant& v, const std::vector<Member>& ms, GroupLaunch* 
     const size_t grid_bytes =
         v.ndim == 1 ? g1d.size() * sizeof(Grid1d<T>) : gnd.size() * sizeof(GridNd<T>);
     gl->off_sync = (gl->off_grids + grid_bytes + 255) & ~(size_t)255;
-    const size_t total = gl->off_sync + sizeof(SyncWords) + ms.size() * sizeof(int);
+    const size_t total = gl->off_sync + sizeof(SyncWords) + ms.size() * kDoneStride * sizeof(int);
     std::vector<unsigned char>& host = gl->image;
     host.assign(total, 0);
     std::memcpy(host.data(), items.data(), items.size() * sizeof(BatchItem));
