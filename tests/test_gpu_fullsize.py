@@ -33,13 +33,13 @@ def run_gpu(p, u0, tuning=None):
 
 
 def report(name, value):
-    """Measured figures (FP32 errors) go to stdout and, on a GPU machine, to a
-    file next to the run's other outputs."""
+    """Measured figures (FP32 errors) go to stdout and, when TVS_REPORT_DIR
+    names a directory, to fp32_errors.txt there."""
     import os
     line = f"{name}: {value:.3e}"
     print(line, flush=True)
-    out = os.path.join(os.environ.get("GRAFT_REPO_ROOT", "."), "gpurun_out")
-    if os.path.isdir(out):
+    out = os.environ.get("TVS_REPORT_DIR")
+    if out and os.path.isdir(out):
         with open(os.path.join(out, "fp32_errors.txt"), "a") as f:
             f.write(line + "\n")
 
