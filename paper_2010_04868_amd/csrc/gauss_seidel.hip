@@ -589,8 +589,17 @@ hipError_t launch_gs_t(const Problem& p, T* grid, const Coeffs<T>& cf, int sweep
     const int nprog = a.nb * sweeps;
     hipLaunchKernelGGL(gs_reset, dim3((unsigned)std::min(1024, (nprog + 255) / 256 + 1)),
                        dim3(256), 0, st, a.ticket, a.progress, nprog);
-    const int waves = std::min(a.nitems, 256 * 8);
+    // as many persistent waves as the device holds at once (one per
+    // workgroup), at most 16 per CU: more items in flight (measured on
+    // 4096^2 FP64: 3072 waves 203.8 GStencil/s, 2048 194.8, 1024 166.2)
     auto go = [&](auto kern) {
+        int per_cu = 0, dev = 0, cus = 256;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)kern, 64, 0) !=
+                hipSuccess || per_cu < 1)
+            per_cu = 8;
+        if (hipGetDevice(&dev) == hipSuccess)
+            (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        const int waves = std::min(a.nitems, std::min(per_cu, 16) * std::max(1, cus));
         hipLaunchKernelGGL(kern, dim3(waves), dim3(64), 0, st, grid, lay, a, cf);
     };
     // sync interval by row width (measured on 600^2 to 4096^2 grids)
